@@ -1,0 +1,267 @@
+"""Pins for the CPU oracle against facts fixed independently of it.
+
+Each test ties one oracle function to something other than itself: a library
+routine that does not use RFR (sympy's factorisation, minimal polynomials,
+integer square roots), a closed form, brute force on tiny inputs, or the
+paper's worked example (Section 2, Eq 5-7).
+"""
+import json
+import math
+import os
+import random
+
+import numpy as np
+import pytest
+import sympy
+
+from oracle import rfr_ref as R
+import workloads as W
+
+X = sympy.Symbol("x")
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def sympy_factor(coeffs):
+    """(content, canonical factors) from sympy.factor_list (Zassenhaus/van Hoeij)."""
+    c, fl = sympy.factor_list(sympy.Poly(list(reversed([int(v) for v in coeffs])), X))
+    c = int(c)
+    facs = []
+    for f, m in fl:
+        cs = [int(v) for v in reversed(f.all_coeffs())]
+        if cs[-1] < 0:
+            cs = [-v for v in cs]
+            c = -c if m % 2 else c
+        facs.extend([cs] * m)
+    return c, R.canonical(facs)
+
+
+def reconstruct(cont, facs):
+    p = [cont]
+    for f in facs:
+        p = R.poly_mul_exact(p, f)
+    return p
+
+
+def sd_poly(k):
+    """Swinnerton-Dyer f_k (Eq 5) as the minimal polynomial of sqrt(2)+...+sqrt(p_k)."""
+    s = sum(sympy.sqrt(sympy.prime(i)) for i in range(1, k + 1))
+    mp = sympy.Poly(sympy.minimal_polynomial(s, X), X)
+    return [int(v) for v in reversed(mp.all_coeffs())]
+
+
+# ---------------------------------------------------------------- textbook
+
+
+@pytest.mark.parametrize("coeffs,expect", [
+    ([6, -5, 1], [(-3, 1), (-2, 1)]),
+    ([-1, 0, 0, 0, 0, 0, 1], [(-1, 1), (1, 1), (1, -1, 1), (1, 1, 1)]),
+    ([0, -1, 0, 1], [(0, 1), (-1, 1), (1, 1)]),
+])
+def test_textbook_factorisations(coeffs, expect):
+    cont, facs = R.factor(coeffs)
+    assert cont == 1
+    assert facs == R.canonical([list(e) for e in expect])
+
+
+def test_linear_product_flood_all_candidates_true():
+    # prod (x - k), k = 1..8: every weight is 0 or 2^64-1 (the floor of a value
+    # within rounding of an integer), so every pattern is a candidate
+    p = [1]
+    for k in range(1, 9):
+        p = R.poly_mul_exact(p, [-k, 1])
+    tr = R.Trace()
+    cont, facs = R.factor(p, tr)
+    assert all(w in (0, (1 << 64) - 1) for w in tr.w)
+    assert len(tr.candidates) == 2 ** 7 - 1
+    assert facs == R.canonical([[-k, 1] for k in range(1, 9)])
+
+
+def test_content_sign_and_x_power():
+    # -6 x (2x - 1)(3x + 1) = -36x^3 + 6x^2 + 6x
+    p = [0, 6, 6, -36]
+    cont, facs = R.factor(p)
+    assert cont == -6
+    assert facs == R.canonical([[0, 1], [-1, 2], [1, 3]])
+    assert reconstruct(cont, facs) == p
+
+
+def test_not_squarefree_raises():
+    with pytest.raises(R.OracleError):
+        R.factor(R.poly_mul_exact([-1, 1], [-1, 1]))
+    with pytest.raises(R.OracleError):
+        R.factor([0, 0, 1, 1])
+
+
+# ---------------------------------------------------------------- paper example
+
+
+def test_swinnerton_dyer_f2_matches_eq6_and_eq7():
+    ex = json.load(open(os.path.join(HERE, "golden", "paper_examples.json")))["sd_f2"]
+    assert sd_poly(2) == ex["coeffs_ascending"]
+    tr = R.Trace()
+    cont, facs = R.factor(ex["coeffs_ascending"], tr)
+    assert facs == [tuple(ex["coeffs_ascending"])]
+    # the four real roots are +-sqrt2 +- sqrt3 (Eq 6)
+    vals = sorted(float(g[1]) for g in tr.groups)
+    want = sorted(float(sympy.sympify(r)) for r in ex["roots"])
+    assert np.allclose(vals, want, rtol=0, atol=1e-12)
+    # Eq 7: dual pairs sum to an integer, so candidates exist, none confirmed
+    assert len(tr.candidates) > 0
+    assert tr.confirmed == {}
+
+
+@pytest.mark.parametrize("k", [3, 4])
+def test_swinnerton_dyer_irreducible_with_candidates(k):
+    p = sd_poly(k)
+    tr = R.Trace()
+    cont, facs = R.factor(p, tr)
+    assert facs == [tuple(p)]
+    assert tr.n == 2 ** k                  # all roots real
+    assert len(tr.candidates) >= 2 ** (2 ** (k - 1) - 1) - 1
+
+
+# ---------------------------------------------------------------- sympy on the configs
+
+
+def test_config_small_matches_sympy():
+    w = W.config_small()
+    got = R.factor(w.coeffs)
+    assert got == sympy_factor(w.coeffs)
+    assert reconstruct(*got) == w.coeffs
+
+
+def test_config_mid_matches_sympy_and_planted():
+    for w in W.config_mid():
+        got = R.factor(w.coeffs)
+        assert got == sympy_factor(w.coeffs), w.seed
+        assert reconstruct(*got) == w.coeffs
+        if w.kind == "planted":
+            for f in w.planted:
+                fp = R.primitive(f)
+                # each planted factor is a product of returned factors
+                rest = fp
+                for q in got[1]:
+                    r = R.exact_divide(rest, list(q))
+                    if r is not None:
+                        rest = r
+                assert rest in ([1], [-1])
+        else:
+            assert len(got[1]) == 1
+
+
+def test_config_batch_sample_matches_sympy():
+    ws = W.config_batch()
+    rnd = random.Random(7)
+    for i in rnd.sample(range(len(ws)), 24):
+        w = ws[i]
+        got = R.factor(w.coeffs)
+        assert got == sympy_factor(w.coeffs), w.seed
+        assert reconstruct(*got) == w.coeffs
+
+
+# ---------------------------------------------------------------- weights (Eq 18)
+
+
+def test_weights_closed_form_sqrt2_and_monic_transform():
+    # roots +-sqrt(2): floor(frac(sqrt2) 2^64) = isqrt(2^129) - 2^64
+    w_pos = math.isqrt(2 << 128) - (1 << 64)
+    w_neg = (1 << 64) - 1 - w_pos          # frac(-sqrt2) = 1 - frac(sqrt2)
+    tr = R.Trace()
+    R.factor([-2, 0, 1], tr)
+    assert sorted(tr.w) == sorted([w_pos, w_neg])
+    # 2x^2 - 1 has roots +-1/sqrt2; its monic transform y^2 - 2 has +-sqrt2
+    tr2 = R.Trace()
+    R.factor([-1, 0, 2], tr2)
+    assert sorted(tr2.w) == sorted([w_pos, w_neg])
+
+
+def test_weights_rational_roots_are_zero():
+    # (2x - 1)(3x + 1): monic-transform roots a_d * (1/2) = 3, a_d * (-1/3) = -2
+    tr = R.Trace()
+    R.factor(R.poly_mul_exact([-1, 2], [1, 3]), tr)
+    assert all(w in (0, (1 << 64) - 1) for w in tr.w)
+    # a quadratic with complex roots: element 2Re z = -b/a, weight frac(-b)=0
+    tr = R.Trace()
+    R.factor([5, 3, 7], tr)   # 7x^2 + 3x + 5, element 7 * (-3/7) = -3
+    assert tr.w in ([0], [(1 << 64) - 1])
+
+
+def test_planted_factor_residue_inside_window():
+    for w in W.config_mid()[8:]:
+        tr = R.Trace()
+        R.factor(w.coeffs, tr)
+        found = [s for s in tr.candidates if s in tr.confirmed]
+        assert found
+        for s in found:
+            tot = sum(tr.w[i] for i in range(tr.n) if (s >> i) & 1)
+            assert R.in_window(tot, tr.t_lo, tr.t_hi)
+
+
+# ---------------------------------------------------------------- searches (Alg A / C)
+
+
+def _py_sums(ws):
+    """Independent subset sums: Python ints, bit i of j selects ws[i]."""
+    return [sum(ws[i] for i in range(len(ws)) if (j >> i) & 1) % (1 << 64)
+            for j in range(1 << len(ws))]
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_brute_equals_hs_equals_python_definition(seed):
+    rng = random.Random(seed)
+    n = rng.randint(2, 15)
+    ws = [rng.getrandbits(64) for _ in range(n)]
+    # plant a few exact relations so the window is hit
+    if n >= 4:
+        ws[1] = (-ws[0] - rng.randint(0, 5)) % (1 << 64)
+        ws[3] = (-(ws[2] + ws[1]) + rng.randint(0, 3)) % (1 << 64)
+    t_lo, t_hi = rng.choice([(0, 0), (n + 3, 2), (7, 9), (1 << 20, 1 << 19)])
+    sums = _py_sums(ws[:n - 1])
+    want = [s for s in range(1, len(sums)) if R.in_window(sums[s], t_lo, t_hi)]
+    assert R.search_brute(ws, t_lo, t_hi) == want
+    assert R.search_hs(ws, t_lo, t_hi) == want
+
+
+def test_search_closed_forms():
+    rng = random.Random(3)
+    n = 12
+    # all weights zero: every nonzero pattern
+    assert R.search_hs([0] * n, 0, 0) == list(range(1, 1 << (n - 1)))
+    # w0 = -w1, the others random 64-bit: only {0, 1}
+    ws = [rng.getrandbits(64) for _ in range(n)]
+    ws[1] = (-ws[0]) % (1 << 64)
+    assert R.search_hs(ws, 0, 0) == [0b11]
+    assert R.search_brute(ws, 0, 0) == [0b11]
+    # distinct powers of two, zero window: no pattern
+    assert R.search_hs([1 << i for i in range(n)], 0, 0) == []
+
+
+def test_window_wraps_across_zero():
+    # sum of pattern {0} is 2^64 - 3: accepted by T_lo >= 3, rejected by T_lo < 3
+    ws = [(1 << 64) - 3, 1 << 40, 1 << 41, 5]
+    assert R.search_hs(ws, 3, 0) == [1]
+    assert R.search_hs(ws, 2, 0) == []
+    assert R.search_brute(ws, 3, 0) == [1]
+
+
+def test_expand_is_sorted_subset_sums():
+    rng = random.Random(11)
+    ws = [rng.getrandbits(64) for _ in range(10)]
+    got = R.expand(ws).tolist()
+    assert got == sorted(_py_sums(ws))
+    neg = R.expand(ws, negate=True).tolist()
+    assert neg == sorted(((-v) % (1 << 64)) for v in _py_sums(ws))
+
+
+# ---------------------------------------------------------------- sizing (Eq 10-11)
+
+
+def test_element_count_near_kac_estimate():
+    ns = []
+    for w in W.config_mid()[:8]:
+        cont, k, prim = R.normalise(w.coeffs)
+        ts, groups, deltas = R.elements(prim)
+        ns.append(len(ts))
+        assert 30 <= len(ts) <= 60        # d/2 <= n <= d (Section 1)
+    est = 60 / 2 + math.log(60) / math.pi
+    assert abs(np.mean(ns) - est) < 3

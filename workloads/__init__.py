@@ -1,0 +1,177 @@
+"""Seeded synthetic inputs for the recombination benchmarks and tests.
+
+This module only draws integer polynomials; it holds none of the factorisation
+arithmetic, so both the product path and the CPU oracle may import it.
+
+Polynomials are lists of Python ints in ascending order: ``c[i]`` is the
+coefficient of ``x**i``.  Every draw uses ``numpy.random.Generator(PCG64(seed))``
+and ``integers(lo, hi + 1)``.
+
+Workload families (sizes follow the paper's benchmark, Section 5: products of
+two random integer polynomials, coefficients drawn uniformly):
+
+* ``config_small``   degree 20: product of two random degree-10 polynomials,
+  coefficients in [-10, 10] (seed 1001).
+* ``config_mid``     degree 60, 16 polynomials: 8 random in [-100, 100] and
+  8 planted products of degree 20 x 40 (seeds 2000..2015).
+* ``config_large``   degree 100, 16 polynomials: 8 random in [-1000, 1000] and
+  8 planted products of degree 30 x 70 (seeds 3000..3015).
+* ``config_batch``   4096 polynomials, degree uniform in [16, 80], even index
+  random, odd index a planted two-factor product (seeds 4000..8095).
+* ``config_stream``  Poisson request stream, degree log-uniform in [24, 128],
+  coefficients in [-1000, 1000], 30 % planted (stream seed 5000).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+__all__ = [
+    "Workload", "rand_poly", "poly_mul", "planted_split",
+    "config_small", "config_mid", "config_large", "config_batch", "config_stream",
+]
+
+
+@dataclass
+class Workload:
+    """One input polynomial plus how it was drawn."""
+    coeffs: List[int]
+    seed: int
+    kind: str                      # "random" or "planted"
+    planted: List[List[int]] = field(default_factory=list)  # the drawn factors
+
+    @property
+    def degree(self) -> int:
+        return len(self.coeffs) - 1
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def rand_poly(rng: np.random.Generator, degree: int, lo: int, hi: int) -> List[int]:
+    """Random integer polynomial of exact degree ``degree``.
+
+    Coefficients are iid uniform in [lo, hi]; the leading and constant
+    coefficients are re-drawn until nonzero.
+    """
+    c = [int(v) for v in rng.integers(lo, hi + 1, size=degree + 1)]
+    while c[0] == 0:
+        c[0] = int(rng.integers(lo, hi + 1))
+    while c[-1] == 0:
+        c[-1] = int(rng.integers(lo, hi + 1))
+    return c
+
+
+def poly_mul(f: List[int], g: List[int]) -> List[int]:
+    """Exact product of two integer polynomials (input construction only)."""
+    out = [0] * (len(f) + len(g) - 1)
+    for i, a in enumerate(f):
+        if a:
+            for j, b in enumerate(g):
+                out[i + j] += a * b
+    return out
+
+
+def planted_split(rng: np.random.Generator, d: int) -> int:
+    """Degree of the smaller planted factor: uniform in [ceil(0.3 d), floor(d/2)]."""
+    lo = max(1, math.ceil(0.3 * d))
+    hi = max(lo, d // 2)
+    return int(rng.integers(lo, hi + 1))
+
+
+def _planted(rng, d1: int, d2: int, lo: int, hi: int, seed: int) -> Workload:
+    f = rand_poly(rng, d1, lo, hi)
+    g = rand_poly(rng, d2, lo, hi)
+    return Workload(poly_mul(f, g), seed, "planted", [f, g])
+
+
+def config_small(seed: int = 1001) -> Workload:
+    """Degree-20 product of two degree-10 polynomials, coefficients in [-10, 10]."""
+    rng = _rng(seed)
+    return _planted(rng, 10, 10, -10, 10, seed)
+
+
+def config_mid(count: int = 16, base_seed: int = 2000) -> List[Workload]:
+    """Degree 60: indices < 8 random in [-100,100]; the rest 20 x 40 products."""
+    out = []
+    for i in range(count):
+        seed = base_seed + i
+        rng = _rng(seed)
+        if i < 8:
+            out.append(Workload(rand_poly(rng, 60, -100, 100), seed, "random"))
+        else:
+            out.append(_planted(rng, 20, 40, -100, 100, seed))
+    return out
+
+
+def config_large(count: int = 16, base_seed: int = 3000) -> List[Workload]:
+    """Degree 100: indices < 8 random in [-1000,1000]; the rest 30 x 70 products."""
+    out = []
+    for i in range(count):
+        seed = base_seed + i
+        rng = _rng(seed)
+        if i < 8:
+            out.append(Workload(rand_poly(rng, 100, -1000, 1000), seed, "random"))
+        else:
+            out.append(_planted(rng, 30, 70, -1000, 1000, seed))
+    return out
+
+
+def config_batch(count: int = 4096, base_seed: int = 4000,
+                 dmin: int = 16, dmax: int = 80) -> List[Workload]:
+    """Uneven batch: degree uniform in [dmin, dmax], coefficients in [-100, 100].
+
+    Even indices are random (almost surely irreducible); odd indices are
+    planted two-factor products with the smaller degree drawn by
+    :func:`planted_split`.
+    """
+    out = []
+    for i in range(count):
+        seed = base_seed + i
+        rng = _rng(seed)
+        d = int(rng.integers(dmin, dmax + 1))
+        if i % 2 == 0:
+            out.append(Workload(rand_poly(rng, d, -100, 100), seed, "random"))
+        else:
+            d1 = planted_split(rng, d)
+            out.append(_planted(rng, d1, d - d1, -100, 100, seed))
+    return out
+
+
+@dataclass
+class Request:
+    """One served request: arrival time (seconds from stream start) + input."""
+    t_arrive: float
+    work: Workload
+
+
+def config_stream(count: int, rate_per_s: float, seed: int = 5000,
+                  dmin: int = 24, dmax: int = 128, p_planted: float = 0.3,
+                  lo: int = -1000, hi: int = 1000,
+                  dcap: Optional[int] = None) -> List[Request]:
+    """Poisson request stream with log-uniform degrees.
+
+    Inter-arrival gaps are exponential with mean ``1/rate_per_s``; the degree is
+    ``round(exp(U(ln dmin, ln dmax)))`` (optionally clipped to ``dcap``); each
+    request is a planted product with probability ``p_planted``.
+    """
+    rng = _rng(seed)
+    t = 0.0
+    out = []
+    for k in range(count):
+        t += float(rng.exponential(1.0 / rate_per_s))
+        d = int(round(math.exp(rng.uniform(math.log(dmin), math.log(dmax)))))
+        if dcap is not None:
+            d = min(d, dcap)
+        sub = _rng(seed * 100003 + k)
+        if float(rng.uniform()) < p_planted and d >= 2:
+            d1 = planted_split(sub, d)
+            w = _planted(sub, d1, d - d1, lo, hi, seed * 100003 + k)
+        else:
+            w = Workload(rand_poly(sub, d, lo, hi), seed * 100003 + k, "random")
+        out.append(Request(t, w))
+    return out
