@@ -1,0 +1,192 @@
+/*
+ * rfr.h -- C ABI of the MI355X Real-Factors-Recombination (RFR) library.
+ *
+ * The library factors a square-free integer polynomial p(x) into irreducible
+ * factors over Z by the method of Iravanian, "Integer Polynomial Factorization
+ * by Recombination of Real Factors" (arXiv 2410.15880):
+ *
+ *   1. the real linear and quadratic factors of p (Section 2, Eq 1) give the
+ *      elements t_i = u_i (real roots) and z_j + conj(z_j) (conjugate pairs);
+ *   2. each element becomes a 64-bit weight w_i = floor(frac(a_d t_i) 2^64)
+ *      (Section 3.3, Eq 18, with the roots of the monic transform, Section 2);
+ *   3. the subset-sum search over the weights runs on the GPU as a
+ *      Horowitz-Sahni meet in the middle (Section 3.3, EXPAND + FIND): both
+ *      halves are enumerated, radix-sorted and band-joined;
+ *   4. every candidate pattern is confirmed by exact trial division on the
+ *      host (Section 2, Algorithm FACTOR), and the irreducible factors are the
+ *      atoms of the divisors found.
+ *
+ * Conventions for every entry point:
+ *   - Polynomials are int64 coefficient arrays in ascending order:
+ *     coeffs[i] multiplies x^i, coeffs[degree] != 0.
+ *   - The return value is the status; nothing is thrown across the ABI.
+ *     rfr_last_error() gives a thread-local message for the last failure.
+ *   - Input arrays are borrowed for the duration of the call only.
+ *   - Results (rfr_result) are owned by the caller after a successful call and
+ *     must be released with rfr_result_free().
+ *   - A context is bound to one HIP device and is not thread-safe: use one
+ *     context per host thread (the serving calls rfr_submit/rfr_poll are the
+ *     exception: they may be called from any thread).
+ */
+#ifndef RFR_H
+#define RFR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rfr_status {
+    RFR_OK = 0,
+    RFR_EINVAL = -1,       /* bad argument: degree < 1, zero leading coeff, NULL */
+    RFR_ENOTSQFREE = -2,   /* p has a repeated factor (the method needs square-free p) */
+    RFR_ENOMEM = -3,       /* device or host allocation failed / over the memory budget */
+    RFR_EPRECISION = -4,   /* roots could not be separated or the accept window is too wide */
+    RFR_EOVERFLOW = -5,    /* a coefficient or element count exceeds the supported range */
+    RFR_ECANDIDATES = -6,  /* more candidate patterns than the candidate capacity */
+    RFR_EDEVICE = -7,      /* a HIP runtime call failed */
+    RFR_EBUSY = -8         /* serving: the request is not finished yet */
+} rfr_status;
+
+/* Largest supported degree and element count (elements = real roots + pairs). */
+#define RFR_MAX_DEGREE 256
+#define RFR_MAX_ELEMENTS 128
+
+typedef struct rfr_ctx rfr_ctx;
+
+/*
+ * Factorisation result: p = content * prod_k factor_k.
+ * Factor k has degree degrees[k] and coefficients
+ * coeffs[off_k .. off_k + degrees[k]] (ascending), off_k = sum_{i<k}(degrees[i]+1).
+ * Factors are primitive, irreducible over Z, with positive leading
+ * coefficient, sorted by (degree, coefficient tuple in ascending-power order).
+ * A factor x is reported when p(0) = 0.
+ */
+typedef struct rfr_result {
+    int64_t content;           /* signed integer content of p */
+    int32_t nfactors;
+    int32_t n_elements;        /* n = r + c (Section 2) */
+    int32_t n_real;            /* r: real roots */
+    int32_t pad_;
+    const int32_t *degrees;    /* [nfactors] */
+    const int64_t *coeffs;     /* [sum(degrees[k]+1)] */
+    uint64_t n_candidates;     /* candidate patterns the search returned */
+    uint64_t n_confirmed;      /* candidates that divide p exactly */
+    uint64_t t_lo, t_hi;       /* accept window: sum in [2^64 - t_lo, 2^64) U [0, t_hi] */
+    double ms_roots;           /* host time: roots, weights, window */
+    double ms_search;          /* recombination search (device) */
+    double ms_confirm;         /* host time: confirmation and atoms */
+} rfr_result;
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device`.  mem_budget_bytes caps the device
+ * memory the context may hold for search tables (0 = 90% of free memory).
+ * Returns RFR_EDEVICE if the device cannot be opened. */
+rfr_status rfr_create(int device, size_t mem_budget_bytes, rfr_ctx **out);
+
+/* Release a context and all device memory it holds (NULL is ignored). */
+void rfr_destroy(rfr_ctx *ctx);
+
+/* Capacity of candidate patterns per polynomial (default 65536). */
+rfr_status rfr_set_candidate_cap(rfr_ctx *ctx, uint64_t cap);
+
+/* ------------------------------------------------------------------ plain */
+
+/* Factor one polynomial (Algorithm FACTOR, Section 2).
+ * coeffs: host array [degree + 1]; degree in [1, RFR_MAX_DEGREE].
+ * The search runs on the context's device; the call blocks until done.
+ * Errors: RFR_EINVAL, RFR_ENOTSQFREE, RFR_EPRECISION, RFR_EOVERFLOW,
+ * RFR_ECANDIDATES, RFR_ENOMEM, RFR_EDEVICE. */
+rfr_status rfr_factor(rfr_ctx *ctx, const int64_t *coeffs, int degree, rfr_result **out);
+
+/* ------------------------------------------------------------------ batched */
+
+/* Factor `count` polynomials in one device pass.
+ * coeffs: all polynomials concatenated, polynomial i occupying
+ *         coeffs[off_i .. off_i + degrees[i]], off_i = sum_{k<i}(degrees[k]+1).
+ * out[i] receives a result (or NULL on failure) and status[i] its status.
+ * The roots run on a host thread pool; the searches of all polynomials run in
+ * one persistent kernel launch (one workgroup per polynomial, largest first),
+ * replayed from a captured HIP graph.  Returns RFR_OK if the batch ran, even
+ * when some entries failed (see status[]). */
+rfr_status rfr_factor_batch(rfr_ctx *ctx, int count, const int64_t *coeffs,
+                            const int32_t *degrees, rfr_result **out, rfr_status *status);
+
+/* ------------------------------------------------------------------ served */
+
+/* Start the serving loop on this context: up to `max_active` requests share
+ * the device at once, each admitted when its search tables fit the memory
+ * budget.  Requests are factored exactly as by rfr_factor. */
+rfr_status rfr_serve_start(rfr_ctx *ctx, int max_active, int host_threads);
+
+/* Queue a request; returns a ticket.  Thread-safe.  The coefficient array is
+ * copied before the call returns. */
+rfr_status rfr_submit(rfr_ctx *ctx, const int64_t *coeffs, int degree, uint64_t *ticket);
+
+/* Collect a finished request: RFR_EBUSY while it runs, otherwise its status,
+ * with *out set on RFR_OK.  A ticket can be collected once.  Thread-safe.
+ * latency_ms (may be NULL) receives submit-to-completion wall time. */
+rfr_status rfr_poll(rfr_ctx *ctx, uint64_t ticket, rfr_result **out, double *latency_ms);
+
+/* Stop the serving loop after draining queued requests. */
+rfr_status rfr_serve_stop(rfr_ctx *ctx);
+
+/* ------------------------------------------------------------------ results */
+
+void rfr_result_free(rfr_result *res);
+const char *rfr_strerror(rfr_status st);
+const char *rfr_last_error(void);
+
+/* ------------------------------------------------------------------ host stages */
+
+/* Elements, weights and window of p (Section 2 and Section 3.3, Eq 18-19):
+ * w_out: host array of at least `degree` entries, receives n weights in
+ * canonical element order (real roots ascending, then conjugate pairs by
+ * (Re, Im)); n_out, n_real_out, t_lo, t_hi receive n, r and the accept
+ * window.  Runs on the host only. */
+rfr_status rfr_weights(const int64_t *coeffs, int degree, uint64_t *w_out, int32_t *n_out,
+                       int32_t *n_real_out, uint64_t *t_lo, uint64_t *t_hi);
+
+/* ------------------------------------------------------------------ kernel level */
+
+/* Device workspace needed by rfr_recombine_dev for n elements. */
+size_t rfr_recombine_workspace_bytes(int n);
+
+/*
+ * The recombination search (Section 3.3, Algorithm C with a FIND that reports
+ * every pair): all patterns s in [1, 2^(n-1)) over the first n-1 weights whose
+ * sum mod 2^64 lies in [2^64 - t_lo, 2^64) U [0, t_hi].
+ *   w_host     host array of n weights (borrowed for the call)
+ *   workspace  device buffer of at least rfr_recombine_workspace_bytes(n)
+ *   hip_stream hipStream_t the work is queued on (NULL = default stream)
+ *   cand_dev   device array of 2*cap uint64: pattern k is split as
+ *              cand_dev[2k] = bits of elements [0, n_a) and
+ *              cand_dev[2k+1] = bits of elements [n_a, n-1) shifted down,
+ *              with n_a = ceil((n-1)/2)
+ *   count_dev  device uint64: number of patterns found; UINT64_MAX if the
+ *              candidate capacity overflowed (then cand_dev is partial)
+ * The call only enqueues work; read count_dev after synchronising the stream.
+ * Requires 2 <= n <= 2 * 34 + 1 and t_lo + t_hi < 2^32; else RFR_EINVAL. */
+rfr_status rfr_recombine_dev(const uint64_t *w_host, int n, uint64_t t_lo, uint64_t t_hi,
+                             void *workspace, size_t ws_bytes, void *hip_stream,
+                             uint64_t *cand_dev, uint64_t cap, uint64_t *count_dev);
+
+/* Device workspace needed by rfr_expand_dev for m weights. */
+size_t rfr_expand_workspace_bytes(int m);
+
+/*
+ * EXPAND (Section 3.3): the 2^m subset sums of m weights (negated first when
+ * `negate` is nonzero), sorted ascending, written to sorted_dev[2^m].
+ * Same kernels as the search (enumerate, partition, tile sort, final sort).
+ * Requires 1 <= m <= 30.  Enqueue only, like rfr_recombine_dev.
+ */
+rfr_status rfr_expand_dev(const uint64_t *w_host, int m, int negate, void *workspace,
+                          size_t ws_bytes, void *hip_stream, uint64_t *sorted_dev);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RFR_H */

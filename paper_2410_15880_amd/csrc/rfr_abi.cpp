@@ -1,0 +1,281 @@
+// C ABI of the RFR library: contexts, plain factorisation, results, host-stage
+// and kernel-level entry points.  Batched and served modes live in
+// rfr_batch.cpp and rfr_serve.cpp.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "rfr_ctx.h"
+
+namespace rfr {
+
+thread_local std::string g_last_error;
+
+rfr_status fail(rfr_status st, const std::string &msg) {
+    g_last_error = msg;
+    return st;
+}
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+rfr_result *pack_result(const Prepared &P, const Factored &F) {
+    size_t nf = F.factors.size();
+    size_t ncoef = 0;
+    for (auto &f : F.factors) ncoef += f.size();
+    size_t bytes = sizeof(rfr_result) + nf * sizeof(int32_t) + 8 + ncoef * sizeof(int64_t);
+    char *mem = (char *)std::calloc(1, bytes);
+    if (!mem) return nullptr;
+    rfr_result *r = (rfr_result *)mem;
+    int32_t *deg = (int32_t *)(mem + sizeof(rfr_result));
+    int64_t *co = (int64_t *)(((uintptr_t)(deg + nf) + 7) & ~(uintptr_t)7);
+    r->content = F.content;
+    r->nfactors = (int32_t)nf;
+    r->n_elements = P.n;
+    r->n_real = P.r;
+    r->degrees = deg;
+    r->coeffs = co;
+    r->n_candidates = F.n_candidates;
+    r->n_confirmed = F.n_confirmed;
+    r->t_lo = P.t_lo;
+    r->t_hi = P.t_hi;
+    size_t k = 0;
+    for (size_t i = 0; i < nf; ++i) {
+        deg[i] = (int32_t)F.factors[i].size() - 1;
+        for (auto c : F.factors[i]) co[k++] = c;
+    }
+    return r;
+}
+
+rfr_status ensure_workspace(rfr_ctx *ctx, Slot &s, size_t need) {
+    if (s.ws_bytes >= need) return RFR_OK;
+    if (s.ws) {
+        (void)hipFree(s.ws);
+        ctx->mem_used -= s.ws_bytes;
+        s.ws = nullptr;
+        s.ws_bytes = 0;
+    }
+    if (ctx->mem_used + need > ctx->budget) return fail(RFR_ENOMEM, "search tables exceed the memory budget");
+    if (hipMalloc(&s.ws, need) != hipSuccess) {
+        s.ws = nullptr;
+        return fail(RFR_ENOMEM, "hipMalloc of the search workspace failed");
+    }
+    s.ws_bytes = need;
+    ctx->mem_used += need;
+    return RFR_OK;
+}
+
+rfr_status slot_init(rfr_ctx *ctx, Slot &s) {
+    if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess)
+        return fail(RFR_EDEVICE, "hipStreamCreate failed");
+    if (hipMalloc(&s.cand_dev, 2 * ctx->cap * sizeof(uint64_t) + 256) != hipSuccess)
+        return fail(RFR_ENOMEM, "hipMalloc of the candidate buffer failed");
+    s.count_dev = (uint64_t *)((char *)s.cand_dev + 2 * ctx->cap * sizeof(uint64_t));
+    if (hipHostMalloc(&s.host, (2 * ctx->cap + 8) * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess)
+        return fail(RFR_ENOMEM, "hipHostMalloc failed");
+    s.cap = ctx->cap;
+    return RFR_OK;
+}
+
+void slot_free(rfr_ctx *ctx, Slot &s) {
+    if (s.ws) {
+        (void)hipFree(s.ws);
+        ctx->mem_used -= s.ws_bytes;
+    }
+    if (s.cand_dev) (void)hipFree(s.cand_dev);
+    if (s.host) (void)hipHostFree(s.host);
+    if (s.stream) (void)hipStreamDestroy(s.stream);
+    s = Slot();
+}
+
+// Device search for a prepared polynomial on one slot; fills cands.
+rfr_status search_on_slot(rfr_ctx *ctx, Slot &s, const Prepared &P, std::vector<Pat> &cands) {
+    cands.clear();
+    if (P.n <= 1) return RFR_OK;
+    if (P.n > 2 * dev::MAX_HALF + 1) return fail(RFR_EOVERFLOW, "too many elements for the search tables");
+    size_t need = recombine_workspace(P.n);
+    rfr_status st = ensure_workspace(ctx, s, need);
+    if (st != RFR_OK) return st;
+    std::string err;
+    st = enqueue_recombine(P.w.data(), P.n, P.t_lo, P.t_hi, s.ws, s.ws_bytes, s.stream, s.cand_dev, s.cap,
+                           s.count_dev, nullptr, err);
+    if (st != RFR_OK) return fail(st, err);
+    uint64_t *hcount = s.host + 2 * s.cap;
+    if (hipMemcpyAsync(hcount, s.count_dev, 8, hipMemcpyDeviceToHost, s.stream) != hipSuccess ||
+        hipStreamSynchronize(s.stream) != hipSuccess)
+        return fail(RFR_EDEVICE, "device search failed");
+    uint64_t cnt = *hcount;
+    if (cnt == ~0ull) return fail(RFR_ECANDIDATES, "candidate capacity exceeded");
+    if (cnt) {
+        if (hipMemcpyAsync(s.host, s.cand_dev, cnt * 16, hipMemcpyDeviceToHost, s.stream) != hipSuccess ||
+            hipStreamSynchronize(s.stream) != hipSuccess)
+            return fail(RFR_EDEVICE, "candidate copy failed");
+    }
+    int na, nb;
+    split_halves(P.n, na, nb);
+    cands.resize(cnt);
+    for (uint64_t k = 0; k < cnt; ++k) {
+        Pat p;
+        uint64_t a = s.host[2 * k], b = s.host[2 * k + 1];
+        for (int i = 0; i < na; ++i)
+            if ((a >> i) & 1) p.set(i);
+        for (int i = 0; i < nb; ++i)
+            if ((b >> i) & 1) p.set(na + i);
+        cands[k] = p;
+    }
+    return RFR_OK;
+}
+
+// Full plain factorisation of one polynomial on one slot.
+rfr_status factor_on_slot(rfr_ctx *ctx, Slot &s, const int64_t *coeffs, int degree, rfr_result **out) {
+    double t0 = now_ms();
+    Prepared P;
+    std::string err;
+    rfr_status st = prepare(coeffs, degree, P, err);
+    if (st != RFR_OK) return fail(st, err);
+    double t1 = now_ms();
+    Factored F;
+    std::vector<Pat> cands;
+    if (P.n <= 1) {
+        trivial_factor(P, F);
+    } else {
+        st = search_on_slot(ctx, s, P, cands);
+        if (st != RFR_OK) return st;
+    }
+    double t2 = now_ms();
+    if (P.n > 1) {
+        st = confirm_and_factor(P, cands, F, err);
+        if (st != RFR_OK) return fail(st, err);
+    }
+    double t3 = now_ms();
+    rfr_result *r = pack_result(P, F);
+    if (!r) return fail(RFR_ENOMEM, "result allocation failed");
+    r->ms_roots = t1 - t0;
+    r->ms_search = t2 - t1;
+    r->ms_confirm = t3 - t2;
+    *out = r;
+    return RFR_OK;
+}
+
+}  // namespace rfr
+
+using namespace rfr;
+
+extern "C" {
+
+rfr_status rfr_create(int device, size_t mem_budget_bytes, rfr_ctx **out) {
+    if (!out) return fail(RFR_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return fail(RFR_EDEVICE, "no such HIP device");
+    if (hipSetDevice(device) != hipSuccess) return fail(RFR_EDEVICE, "hipSetDevice failed");
+    rfr_ctx *ctx = new (std::nothrow) rfr_ctx();
+    if (!ctx) return fail(RFR_ENOMEM, "context allocation failed");
+    ctx->device = device;
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+        delete ctx;
+        return fail(RFR_EDEVICE, "hipMemGetInfo failed");
+    }
+    ctx->budget = mem_budget_bytes ? mem_budget_bytes : (size_t)(0.9 * (double)fr);
+    rfr_status st = slot_init(ctx, ctx->main);
+    if (st != RFR_OK) {
+        slot_free(ctx, ctx->main);
+        delete ctx;
+        return st;
+    }
+    *out = ctx;
+    return RFR_OK;
+}
+
+void rfr_destroy(rfr_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    rfr_serve_stop(ctx);
+    batch_release(ctx);
+    slot_free(ctx, ctx->main);
+    delete ctx;
+}
+
+rfr_status rfr_set_candidate_cap(rfr_ctx *ctx, uint64_t cap) {
+    if (!ctx || cap < 1 || cap > (1ull << 26)) return fail(RFR_EINVAL, "cap must be in [1, 2^26]");
+    if (ctx->serving) return fail(RFR_EBUSY, "cannot change the cap while serving");
+    (void)hipSetDevice(ctx->device);
+    size_t ws = ctx->main.ws_bytes;
+    slot_free(ctx, ctx->main);
+    ctx->cap = cap;
+    rfr_status st = slot_init(ctx, ctx->main);
+    (void)ws;
+    return st;
+}
+
+rfr_status rfr_factor(rfr_ctx *ctx, const int64_t *coeffs, int degree, rfr_result **out) {
+    if (!ctx || !out) return fail(RFR_EINVAL, "ctx/out is NULL");
+    *out = nullptr;
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(RFR_EDEVICE, "hipSetDevice failed");
+    return factor_on_slot(ctx, ctx->main, coeffs, degree, out);
+}
+
+void rfr_result_free(rfr_result *res) { std::free(res); }
+
+const char *rfr_strerror(rfr_status st) {
+    switch (st) {
+        case RFR_OK: return "ok";
+        case RFR_EINVAL: return "invalid argument";
+        case RFR_ENOTSQFREE: return "polynomial is not square-free";
+        case RFR_ENOMEM: return "out of memory or over budget";
+        case RFR_EPRECISION: return "roots not separated / window too wide";
+        case RFR_EOVERFLOW: return "value outside the supported range";
+        case RFR_ECANDIDATES: return "candidate capacity exceeded";
+        case RFR_EDEVICE: return "HIP runtime error";
+        case RFR_EBUSY: return "not finished";
+    }
+    return "unknown status";
+}
+
+const char *rfr_last_error(void) { return g_last_error.c_str(); }
+
+rfr_status rfr_weights(const int64_t *coeffs, int degree, uint64_t *w_out, int32_t *n_out,
+                       int32_t *n_real_out, uint64_t *t_lo, uint64_t *t_hi) {
+    if (!w_out || !n_out || !n_real_out || !t_lo || !t_hi) return fail(RFR_EINVAL, "NULL output");
+    Prepared P;
+    std::string err;
+    rfr_status st = prepare(coeffs, degree, P, err);
+    if (st != RFR_OK) return fail(st, err);
+    for (int i = 0; i < P.n; ++i) w_out[i] = P.w[i];
+    *n_out = P.n;
+    *n_real_out = P.r;
+    *t_lo = P.t_lo;
+    *t_hi = P.t_hi;
+    return RFR_OK;
+}
+
+size_t rfr_recombine_workspace_bytes(int n) { return recombine_workspace(n); }
+
+rfr_status rfr_recombine_dev(const uint64_t *w_host, int n, uint64_t t_lo, uint64_t t_hi, void *workspace,
+                             size_t ws_bytes, void *hip_stream, uint64_t *cand_dev, uint64_t cap,
+                             uint64_t *count_dev) {
+    std::string err;
+    rfr_status st = enqueue_recombine(w_host, n, t_lo, t_hi, workspace, ws_bytes, (hipStream_t)hip_stream,
+                                      cand_dev, cap, count_dev, nullptr, err);
+    if (st != RFR_OK) return fail(st, err);
+    return RFR_OK;
+}
+
+size_t rfr_expand_workspace_bytes(int m) { return expand_workspace(m); }
+
+rfr_status rfr_expand_dev(const uint64_t *w_host, int m, int negate, void *workspace, size_t ws_bytes,
+                          void *hip_stream, uint64_t *sorted_dev) {
+    std::string err;
+    rfr_status st = enqueue_expand(w_host, m, negate, workspace, ws_bytes, (hipStream_t)hip_stream, sorted_dev, err);
+    if (st != RFR_OK) return fail(st, err);
+    return RFR_OK;
+}
+
+}  // extern "C"

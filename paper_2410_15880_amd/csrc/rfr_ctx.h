@@ -1,0 +1,77 @@
+// Context, device slots and the shared helpers of the ABI, batch and serving
+// translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "rfr_device.h"
+#include "rfr_internal.h"
+
+namespace rfr {
+
+// One device lane of work: a stream, a search workspace (grown on demand) and
+// candidate buffers (device + pinned host).
+struct Slot {
+    hipStream_t stream = nullptr;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    uint64_t *cand_dev = nullptr;
+    uint64_t *count_dev = nullptr;
+    uint64_t *host = nullptr;  // pinned: [2*cap] candidates + count
+    uint64_t cap = 0;
+    bool busy = false;
+};
+
+struct Request {
+    uint64_t ticket = 0;
+    std::vector<int64_t> coeffs;
+    double t_submit = 0, t_done = 0;
+    rfr_status status = RFR_EBUSY;
+    rfr_result *result = nullptr;
+};
+
+struct BatchState;  // persistent-kernel batch resources (rfr_batch.cpp)
+
+}  // namespace rfr
+
+struct rfr_ctx {
+    int device = 0;
+    size_t budget = 0;
+    size_t mem_used = 0;         // bytes of search workspaces held
+    uint64_t cap = 65536;        // candidate patterns per polynomial
+    rfr::Slot main;              // slot of the plain path
+    // ---- serving
+    bool serving = false;
+    std::vector<rfr::Slot> slots;
+    std::vector<std::thread> workers;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_slot;
+    std::deque<rfr::Request *> queue;
+    std::map<uint64_t, rfr::Request *> reqs;
+    uint64_t next_ticket = 1;
+    bool stopping = false;
+    // ---- batch
+    rfr::BatchState *batch = nullptr;
+};
+
+namespace rfr {
+extern thread_local std::string g_last_error;
+rfr_status fail(rfr_status st, const std::string &msg);
+double now_ms();
+rfr_result *pack_result(const Prepared &P, const Factored &F);
+rfr_status ensure_workspace(rfr_ctx *ctx, Slot &s, size_t need);
+rfr_status slot_init(rfr_ctx *ctx, Slot &s);
+void slot_free(rfr_ctx *ctx, Slot &s);
+rfr_status search_on_slot(rfr_ctx *ctx, Slot &s, const Prepared &P, std::vector<Pat> &cands);
+rfr_status factor_on_slot(rfr_ctx *ctx, Slot &s, const int64_t *coeffs, int degree, rfr_result **out);
+void batch_release(rfr_ctx *ctx);
+}  // namespace rfr

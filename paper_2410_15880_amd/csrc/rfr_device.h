@@ -1,0 +1,104 @@
+// Device pipeline of the recombination search: tunables, argument structs and
+// the host-side enqueue entry points (implemented in rfr_device.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "rfr_internal.h"
+
+namespace rfr {
+
+namespace dev {
+// ---- K0/K1/K4: Gray-code enumeration (256 lanes own the low 8 pattern bits)
+constexpr int NT1 = 256;          // threads per workgroup
+constexpr int KPT1 = 16;          // Gray steps (keys per thread) per LDS tile
+constexpr int T1 = NT1 * KPT1;    // keys per K1 tile (32 KB of LDS)
+constexpr int TILES1 = 8;         // tiles per K0/K1 workgroup
+constexpr int MAXB1_LOG = 10;     // level-1 digit bits (buckets) at most
+constexpr int MAXB1 = 1 << MAXB1_LOG;
+// ---- K2: per-bucket tile sort by the level-2 digit
+constexpr int NT2 = 512;
+constexpr int T2 = 8192;          // keys per tile (<= 65535: u16 digit offsets)
+constexpr int KPT2 = T2 / NT2;
+constexpr int MAXB2_LOG = 10;
+constexpr int MAXB2 = 1 << MAXB2_LOG;
+// ---- K3: sub-bucket gather, LDS sort, merge-path band join
+constexpr int NT3 = 256;
+constexpr int CAP3 = 2048;        // keys per half held in LDS (mean is ~1024)
+constexpr int KPT3 = CAP3 / NT3;
+constexpr int LB3 = 10;           // bits of the in-LDS counting sort
+constexpr int NB3 = 1 << LB3;
+constexpr int MAXT = 256;         // tile rows staged per gather chunk
+// ---- K4/K5: candidate keys -> patterns
+constexpr int KCAP_MAX = 4096;    // key pairs held per search
+constexpr int RBITS_LOG = 16;     // LDS bitmap of candidate-key prefixes
+constexpr int RBITS = 1 << RBITS_LOG;
+constexpr int MAX_HALF = 34;      // elements per half (2^34 keys)
+
+struct HalfArgs {
+    uint64_t *keys;      // [N] partitioned keys
+    uint64_t *hist1;     // [2^B1][nwg1] counts, then exclusive prefixes
+    uint64_t *bstart;    // [2^B1 + 1] bucket starts
+    uint32_t *tstart;    // [2^B1 + 1] first level-2 tile of each bucket
+    uint16_t *digstart;  // [2^B2 + 1][ntile2_max] digit offsets inside each tile
+    uint64_t N;          // 2^m
+    uint64_t steps;      // 2^(m - L) Gray steps
+    uint32_t spw;        // Gray steps per K0/K1/K4 workgroup
+    uint32_t nwg1;       // K0/K1/K4 workgroups
+    uint32_t ntile2_max; // level-2 tile capacity
+    int m, L;            // weights in this half, lane bits
+};
+
+struct JobArgs {
+    HalfArgs h[2];              // 0 = half A, 1 = half B' (negated)
+    uint64_t wts[2][MAX_HALF];  // weights of each half (B' already negated)
+    int B1, B2;                 // level-1 / level-2 digit bits
+    uint64_t t_lo, t_hi;        // accept window
+    uint64_t *kp;               // [2*kcap] candidate key pairs (a, b')
+    uint64_t *kp_count;
+    uint64_t kcap;
+    uint64_t *rec;              // [2][kcap][2] (key, pattern) per half
+    uint32_t *rec_count;        // [2]
+    uint64_t *out;              // [2*cap] pattern pairs
+    uint64_t *out_count;
+    uint64_t cap;
+    uint32_t *flags;            // bit 0: sort overflow, bit 1: join fallback used
+};
+}  // namespace dev
+
+struct HalfPlan {
+    int m = 0, L = 0;
+    uint64_t N = 0, steps = 0;
+    uint32_t spw = 0, nwg1 = 0, ntile2_max = 0;
+    dev::HalfArgs a{};
+};
+
+struct JobPlan {
+    int nhalves = 2;
+    HalfPlan h[2];
+    int B1 = 0, B2 = 0;
+    uint64_t *kp = nullptr, *rec = nullptr, *counters = nullptr;
+};
+
+// Optional events recorded between stages (any entry may be null):
+// 0 start, 1 after count, 2 after scans, 3 after K1, 4 after K2, 5 after K3, 6 end.
+struct StageEvents {
+    void *ev[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+};
+
+// Workspace bytes for a search of half sizes (na, nb); nb < 0 = one half only.
+uint64_t plan_job(int na, int nb, JobPlan &P);
+size_t recombine_workspace(int n);
+size_t expand_workspace(int m);
+
+rfr_status enqueue_recombine(const uint64_t *w, int n, uint64_t t_lo, uint64_t t_hi, void *ws,
+                             size_t ws_bytes, hipStream_t st, uint64_t *cand, uint64_t cap,
+                             uint64_t *count, StageEvents *ev, std::string &err);
+rfr_status enqueue_expand(const uint64_t *w, int m, int negate, void *ws, size_t ws_bytes,
+                          hipStream_t st, uint64_t *sorted, std::string &err);
+
+}  // namespace rfr

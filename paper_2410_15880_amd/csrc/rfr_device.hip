@@ -1,0 +1,883 @@
+// Device side of the RFR recombination search for gfx950 (CDNA4, wave64).
+//
+// Paper: Iravanian, arXiv 2410.15880, Section 3.3 (Algorithm C = EXPAND both
+// halves, sort, FIND).  The weights are the 64-bit integers of Eq 18; a pattern
+// is accepted when its sum mod 2^64 lies in [2^64 - t_lo, 2^64) U [0, t_hi]
+// (the integer form of Eq 19 widened by the quantisation and root error).
+//
+// Pipeline for one search over n-1 weights split into half A (n_a weights) and
+// half B (n_b weights); half B is enumerated negated (B' = -B) so a match is
+// A ~ B' within the window:
+//   K0 k_enum<true>   Gray-code enumeration, level-1 digit histogram per WG
+//   S1 k_scan_cols    per-bucket exclusive prefix over WGs
+//   S2 k_scan_buckets bucket starts and level-2 tile table
+//   K1 k_enum<false>  Gray-code enumeration, LDS counting sort of each tile by
+//                     the level-1 digit, run-coalesced stores into buckets
+//   K2 k_tile2        LDS counting sort of each bucket tile by the level-2
+//                     digit, written back in place + per-digit tile offsets
+//   K3 k_join         per sub-bucket (level-1 + level-2 prefix): gather both
+//                     halves, LDS radix sort on the next digit + insertion,
+//                     merge-path band join emitting every key pair in window
+//   K4 k_recover      compute-only re-enumeration mapping candidate keys back
+//                     to patterns
+//   K5 k_pairs        one workgroup: de-duplicate key pairs, expand them into
+//                     pattern pairs
+// All arithmetic on keys is exact wrapping uint64.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <algorithm>
+#include <cstring>
+
+#include "rfr_device.h"
+
+namespace rfr {
+namespace dev {
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ uint32_t dig(uint64_t key, int shift, uint32_t mask) {
+    return shift >= 64 ? 0u : (uint32_t)(key >> shift) & mask;
+}
+
+// Inclusive scan across one wavefront (64 lanes).
+__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint64_t t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan of one value per thread across the workgroup; returns the
+// exclusive prefix and writes the block total to *total (all threads).
+template <int NTH>
+__device__ __forceinline__ uint64_t block_excl_scan(uint64_t v, uint64_t *s_tmp, uint64_t *total) {
+    constexpr int NW = NTH / 64;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint64_t inc = wave_incl_scan(v);
+    if (lane == 63) s_tmp[wv] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t acc = 0;
+        for (int i = 0; i < NW; ++i) {
+            uint64_t t = s_tmp[i];
+            s_tmp[i] = acc;
+            acc += t;
+        }
+        s_tmp[NW] = acc;
+    }
+    __syncthreads();
+    uint64_t r = inc - v + s_tmp[wv];
+    *total = s_tmp[NW];
+    __syncthreads();
+    return r;
+}
+
+// Exclusive scan, in place, of an LDS array of n <= NTH*PER entries.
+template <int NTH, int PER, typename T>
+__device__ __forceinline__ uint64_t lds_excl_scan(T *a, int n, uint64_t *s_tmp) {
+    uint64_t loc[PER];
+    uint64_t sum = 0;
+    const int base = threadIdx.x * PER;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        loc[k] = (base + k < n) ? (uint64_t)a[base + k] : 0;
+        sum += loc[k];
+    }
+    uint64_t tot;
+    uint64_t pre = block_excl_scan<NTH>(sum, s_tmp, &tot);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        if (base + k < n) a[base + k] = (T)pre;
+        pre += loc[k];
+    }
+    __syncthreads();
+    return tot;
+}
+
+// Cyclic window test on d = b' - a (mod 2^64): d in [2^64 - t_hi, 2^64) U [0, t_lo].
+__device__ __forceinline__ bool in_win(uint64_t a, uint64_t b, uint64_t t_lo, uint64_t t_hi) {
+    uint64_t dlt = b - a;
+    return dlt <= t_lo || (0 - dlt) <= t_hi;
+}
+
+__device__ __forceinline__ void emit_pair(const JobArgs &J, uint64_t a, uint64_t b) {
+    unsigned long long idx = atomicAdd((unsigned long long *)J.kp_count, 1ull);
+    if (idx < J.kcap) {
+        J.kp[2 * idx] = a;
+        J.kp[2 * idx + 1] = b;
+    }
+}
+
+// ------------------------------------------------------------------ init
+__global__ void k_init(JobArgs J) {
+    if (threadIdx.x == 0) {
+        *J.kp_count = 0;
+        J.rec_count[0] = 0;
+        J.rec_count[1] = 0;
+        if (J.out_count) *J.out_count = 0;
+        *J.flags = 0;
+    }
+}
+
+// ------------------------------------------------------------------ K0 / K1
+// Work of one workgroup: Gray-code steps [h0, h1) of its half.  Lane l owns the
+// low L pattern bits (its partial sum is fixed); step h selects the high bits
+// gray(h) = h ^ (h >> 1), so going from h to h+1 flips exactly bit ctz(h+1) and
+// changes the high sum by one wavefront-uniform +-w.
+template <bool COUNT>
+__global__ __launch_bounds__(NT1) void k_enum(JobArgs J) {
+    const HalfArgs &H = J.h[blockIdx.y];
+    const uint32_t wg = blockIdx.x;
+    if (wg >= H.nwg1) return;
+    const int B1 = J.B1;
+    const int nb = 1 << B1;
+    const int sh1 = 64 - B1;
+    const uint32_t m1 = (uint32_t)nb - 1;
+    const int tid = threadIdx.x;
+    const int nl = 1 << H.L;
+    const bool act = tid < nl;
+
+    __shared__ uint64_t s_w[64];
+    __shared__ uint32_t s_cnt[MAXB1];
+    __shared__ uint32_t s_off[MAXB1];
+    __shared__ uint64_t s_cur[MAXB1];
+    __shared__ uint64_t s_tmp[NT1 / 64 + 1];
+    __shared__ uint64_t s_buf[COUNT ? 1 : T1];
+
+    if (tid < H.m) s_w[tid] = J.wts[blockIdx.y][tid];
+    for (int b = tid; b < nb; b += NT1) {
+        s_cnt[b] = 0;
+        if (!COUNT) s_cur[b] = H.bstart[b] + H.hist1[(size_t)b * H.nwg1 + wg];
+    }
+    __syncthreads();
+
+    uint64_t slo = 0;
+    for (int i = 0; i < H.L; ++i)
+        if ((tid >> i) & 1) slo += s_w[i];
+    const uint64_t h0 = (uint64_t)wg * H.spw;
+    const uint64_t h1 = min(h0 + (uint64_t)H.spw, H.steps);
+    uint64_t g = h0 ^ (h0 >> 1);
+    uint64_t shi = 0;
+    for (int i = 0; i < H.m - H.L; ++i)
+        if ((g >> i) & 1) shi += s_w[H.L + i];
+
+    for (uint64_t h = h0; h < h1; h += KPT1) {
+        const int ns = (int)min((uint64_t)KPT1, h1 - h);
+        uint64_t key[KPT1];
+#pragma unroll
+        for (int k = 0; k < KPT1; ++k) {
+            key[k] = slo + shi;
+            const uint64_t t = h + k + 1;
+            if (k < ns && t < h1) {
+                const int b = __builtin_ctzll(t);
+                g ^= 1ull << b;
+                const uint64_t wb = s_w[H.L + b];
+                shi += ((g >> b) & 1) ? wb : (0 - wb);
+            }
+        }
+        if (COUNT) {
+#pragma unroll
+            for (int k = 0; k < KPT1; ++k)
+                if (act && k < ns) atomicAdd(&s_cnt[dig(key[k], sh1, m1)], 1u);
+            continue;
+        }
+        uint32_t rank[KPT1];
+#pragma unroll
+        for (int k = 0; k < KPT1; ++k)
+            if (act && k < ns) rank[k] = atomicAdd(&s_cnt[dig(key[k], sh1, m1)], 1u);
+        __syncthreads();
+        for (int b = tid; b < nb; b += NT1) s_off[b] = s_cnt[b];
+        __syncthreads();
+        lds_excl_scan<NT1, MAXB1 / NT1>(s_off, nb, s_tmp);
+#pragma unroll
+        for (int k = 0; k < KPT1; ++k)
+            if (act && k < ns) {
+                const uint32_t d = dig(key[k], sh1, m1);
+                s_buf[s_off[d] + rank[k]] = key[k];
+            }
+        __syncthreads();
+        const int tile = ns * nl;
+        for (int p = tid; p < tile; p += NT1) {
+            const uint64_t kk = s_buf[p];
+            const uint32_t d = dig(kk, sh1, m1);
+            H.keys[s_cur[d] + (uint64_t)(p - (int)s_off[d])] = kk;
+        }
+        __syncthreads();
+        for (int b = tid; b < nb; b += NT1) {
+            s_cur[b] += s_cnt[b];
+            s_cnt[b] = 0;
+        }
+        __syncthreads();
+    }
+    if (COUNT) {
+        __syncthreads();
+        for (int b = tid; b < nb; b += NT1) H.hist1[(size_t)b * H.nwg1 + wg] = s_cnt[b];
+    }
+}
+
+// ------------------------------------------------------------------ S1 / S2
+// Column prefix: hist1[b][w] becomes the exclusive prefix over w; the bucket
+// total goes to bstart[b] (turned into bucket starts by S2).
+__global__ __launch_bounds__(NT1) void k_scan_cols(JobArgs J) {
+    const HalfArgs &H = J.h[blockIdx.y];
+    const int b = blockIdx.x;
+    if (b >= (1 << J.B1)) return;
+    __shared__ uint64_t s_tmp[NT1 / 64 + 1];
+    uint64_t *col = H.hist1 + (size_t)b * H.nwg1;
+    uint64_t carry = 0;
+    for (uint32_t base = 0; base < H.nwg1; base += NT1) {
+        const uint32_t i = base + threadIdx.x;
+        const uint64_t v = i < H.nwg1 ? col[i] : 0;
+        uint64_t tot;
+        const uint64_t ex = block_excl_scan<NT1>(v, s_tmp, &tot);
+        if (i < H.nwg1) col[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) H.bstart[b] = carry;
+}
+
+__global__ __launch_bounds__(NT1) void k_scan_buckets(JobArgs J) {
+    const HalfArgs &H = J.h[blockIdx.y];
+    const int nb = 1 << J.B1;
+    __shared__ uint64_t s_tmp[NT1 / 64 + 1];
+    uint64_t carry = 0, tcarry = 0;
+    for (int base = 0; base < nb; base += NT1) {
+        const int i = base + threadIdx.x;
+        const uint64_t v = i < nb ? H.bstart[i] : 0;
+        const uint64_t nt = (v + T2 - 1) / T2;
+        uint64_t tot, ttot;
+        const uint64_t ex = block_excl_scan<NT1>(v, s_tmp, &tot);
+        const uint64_t tex = block_excl_scan<NT1>(nt, s_tmp, &ttot);
+        if (i < nb) {
+            H.bstart[i] = carry + ex;
+            H.tstart[i] = (uint32_t)(tcarry + tex);
+        }
+        carry += tot;
+        tcarry += ttot;
+    }
+    if (threadIdx.x == 0) {
+        H.bstart[nb] = carry;
+        H.tstart[nb] = (uint32_t)tcarry;
+    }
+}
+
+// ------------------------------------------------------------------ K2
+// One tile (<= T2 keys) of one level-1 bucket: counting sort by the level-2
+// digit in LDS, written back in place; digstart[d][tile] = offset of digit d
+// inside the tile, digstart[nd][tile] = tile length.
+__global__ __launch_bounds__(NT2) void k_tile2(JobArgs J) {
+    const HalfArgs &H = J.h[blockIdx.y];
+    const int nb = 1 << J.B1;
+    const uint32_t tile = blockIdx.x;
+    const uint32_t ntiles = H.tstart[nb];
+    if (tile >= ntiles) return;
+    const int nd = 1 << J.B2;
+    const int sh2 = 64 - J.B1 - J.B2;
+    const uint32_t m2 = (uint32_t)nd - 1;
+    const int tid = threadIdx.x;
+
+    __shared__ uint64_t s_buf[T2];
+    __shared__ uint32_t s_cnt[MAXB2];
+    __shared__ uint32_t s_off[MAXB2];
+    __shared__ uint64_t s_tmp[NT2 / 64 + 1];
+    __shared__ int s_b;
+
+    if (tid == 0) {
+        int lo = 0, hi = nb - 1;  // largest b with tstart[b] <= tile
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (H.tstart[mid] <= tile) lo = mid;
+            else hi = mid - 1;
+        }
+        s_b = lo;
+    }
+    for (int d = tid; d < nd; d += NT2) s_cnt[d] = 0;
+    __syncthreads();
+    const int b = s_b;
+    const uint64_t base = H.bstart[b] + (uint64_t)(tile - H.tstart[b]) * T2;
+    const int len = (int)min((uint64_t)T2, H.bstart[b + 1] - base);
+
+    uint64_t key[KPT2];
+    uint32_t rank[KPT2];
+#pragma unroll
+    for (int k = 0; k < KPT2; ++k) {
+        const int p = tid + k * NT2;
+        if (p < len) {
+            key[k] = H.keys[base + p];
+            rank[k] = atomicAdd(&s_cnt[dig(key[k], sh2, m2)], 1u);
+        }
+    }
+    __syncthreads();
+    for (int d = tid; d < nd; d += NT2) s_off[d] = s_cnt[d];
+    __syncthreads();
+    lds_excl_scan<NT2, MAXB2 / NT2>(s_off, nd, s_tmp);
+#pragma unroll
+    for (int k = 0; k < KPT2; ++k) {
+        const int p = tid + k * NT2;
+        if (p < len) s_buf[s_off[dig(key[k], sh2, m2)] + rank[k]] = key[k];
+    }
+    __syncthreads();
+    for (int p = tid; p < len; p += NT2) H.keys[base + p] = s_buf[p];
+    for (int d = tid; d < nd; d += NT2) H.digstart[(size_t)d * H.ntile2_max + tile] = (uint16_t)s_off[d];
+    if (tid == 0) H.digstart[(size_t)nd * H.ntile2_max + tile] = (uint16_t)len;
+}
+
+// ------------------------------------------------------------------ K3
+// Shared state of one sub-bucket of one half, gathered into LDS.
+struct SubRef {
+    uint32_t t0, t1;  // tile range of the level-1 bucket
+    uint64_t pos0;    // bucket start
+};
+
+__device__ __forceinline__ SubRef sub_ref(const HalfArgs &H, int b) {
+    SubRef r;
+    r.t0 = H.tstart[b];
+    r.t1 = H.tstart[b + 1];
+    r.pos0 = H.bstart[b];
+    return r;
+}
+
+// Visit every key of sub-bucket (b, d) of half H directly from global memory.
+template <typename F>
+__device__ __forceinline__ void for_each_global(const HalfArgs &H, int B2, int b, int d, F f) {
+    const SubRef r = sub_ref(H, b);
+    for (uint32_t t = r.t0; t < r.t1; ++t) {
+        const uint32_t s = H.digstart[(size_t)d * H.ntile2_max + t];
+        const uint32_t e = H.digstart[(size_t)(d + 1) * H.ntile2_max + t];
+        const uint64_t tb = r.pos0 + (uint64_t)(t - r.t0) * T2;
+        for (uint32_t q = s; q < e; ++q)
+            if (!f(H.keys[tb + q])) return;
+    }
+}
+
+// Gather sub-bucket (b, d) of half H into s_keys; returns its size (may
+// exceed CAP3, in which case nothing beyond CAP3 is stored).
+__device__ uint32_t gather_sub(const HalfArgs &H, int B2, int b, int d, uint64_t *s_keys,
+                               uint32_t *s_st, uint32_t *s_len, uint64_t *s_tmp) {
+    const SubRef r = sub_ref(H, b);
+    const uint32_t nt = r.t1 - r.t0;
+    uint32_t total = 0;
+    // tile rows in chunks of MAXT tiles
+    for (uint32_t c0 = 0; c0 < nt; c0 += MAXT) {
+        const uint32_t cn = min((uint32_t)MAXT, nt - c0);
+        for (uint32_t i = threadIdx.x; i < cn; i += NT3) {
+            const uint32_t t = r.t0 + c0 + i;
+            const uint32_t s = H.digstart[(size_t)d * H.ntile2_max + t];
+            const uint32_t e = H.digstart[(size_t)(d + 1) * H.ntile2_max + t];
+            s_st[i] = s;
+            s_len[i] = e - s;
+        }
+        __syncthreads();
+        // prefix of lengths (serial per wave is enough: cn <= MAXT)
+        if (threadIdx.x == 0) {
+            uint32_t acc = total;
+            for (uint32_t i = 0; i < cn; ++i) {
+                const uint32_t l = s_len[i];
+                s_len[i] = acc;  // becomes the LDS destination offset
+                acc += l;
+            }
+            s_tmp[0] = acc;
+        }
+        __syncthreads();
+        const uint32_t acc = (uint32_t)s_tmp[0];
+        // one wavefront per tile segment
+        const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        for (uint32_t i = wv; i < cn; i += NT3 / 64) {
+            const uint32_t dst = s_len[i];
+            const uint32_t end = (i + 1 < cn) ? s_len[i + 1] : acc;
+            const uint32_t len = end - dst;
+            const uint64_t src = r.pos0 + (uint64_t)(c0 + i) * T2 + s_st[i];
+            for (uint32_t q = lane; q < len; q += 64)
+                if (dst + q < CAP3) s_keys[dst + q] = H.keys[src + q];
+        }
+        total = acc;
+        __syncthreads();
+    }
+    return total;
+}
+
+// Counting sort of s_keys[0..cnt) by the B3-bit digit at shift sh3, in place
+// (keys staged in registers), then insertion sort inside each digit bin: the
+// result is fully sorted.  s_bin must hold NB3 + 1 entries.
+__device__ void lds_sort(uint64_t *s_keys, uint32_t cnt, int sh3, uint32_t *s_bin, uint64_t *s_tmp) {
+    for (int i = threadIdx.x; i < NB3; i += NT3) s_bin[i] = 0;
+    __syncthreads();
+    uint64_t key[KPT3];
+    uint32_t rank[KPT3];
+#pragma unroll
+    for (int k = 0; k < KPT3; ++k) {
+        const uint32_t p = threadIdx.x + k * NT3;
+        if (p < cnt) {
+            key[k] = s_keys[p];
+            rank[k] = atomicAdd(&s_bin[dig(key[k], sh3, NB3 - 1)], 1u);
+        }
+    }
+    __syncthreads();
+    lds_excl_scan<NT3, NB3 / NT3>(s_bin, NB3, s_tmp);
+    if (threadIdx.x == 0) s_bin[NB3] = cnt;
+#pragma unroll
+    for (int k = 0; k < KPT3; ++k) {
+        const uint32_t p = threadIdx.x + k * NT3;
+        if (p < cnt) s_keys[s_bin[dig(key[k], sh3, NB3 - 1)] + rank[k]] = key[k];
+    }
+    __syncthreads();
+    for (int bn = threadIdx.x; bn < NB3; bn += NT3) {
+        const uint32_t s = s_bin[bn], e = s_bin[bn + 1];
+        for (uint32_t i = s + 1; i < e; ++i) {
+            const uint64_t v = s_keys[i];
+            uint32_t j = i;
+            while (j > s && s_keys[j - 1] > v) {
+                s_keys[j] = s_keys[j - 1];
+                --j;
+            }
+            s_keys[j] = v;
+        }
+    }
+    __syncthreads();
+}
+
+// Partners of a in a neighbouring sub-bucket `ns` of half B' (slow path, rare):
+// every key b there with b' - a in the window, except those the in-bucket
+// merge already reported (b in [lo, hi] and inside sub-bucket s).
+__device__ void edge_scan(const JobArgs &J, uint64_t a, uint32_t s, uint32_t ns, uint64_t lo, uint64_t hi) {
+    const int LB = J.B1 + J.B2;
+    const HalfArgs &HB = J.h[1];
+    const int b = (int)(ns >> J.B2), d = (int)(ns & ((1u << J.B2) - 1));
+    for_each_global(HB, J.B2, b, d, [&](uint64_t bk) {
+        const bool in_s = LB == 0 || (uint32_t)(bk >> (64 - LB)) == s;
+        if (in_win(a, bk, J.t_lo, J.t_hi) && !(in_s && bk >= lo && bk <= hi)) emit_pair(J, a, bk);
+        return *J.kp_count <= J.kcap;
+    });
+}
+
+template <bool SORT_OUT>
+__global__ __launch_bounds__(NT3) void k_join(JobArgs J, uint64_t *sorted_out) {
+    const int LB = J.B1 + J.B2;
+    const uint32_t NS = 1u << LB;
+    const uint32_t s = blockIdx.x;
+    if (s >= NS) return;
+    const int b = (int)(s >> J.B2), d = (int)(s & ((1u << J.B2) - 1));
+    const int sh3 = 64 - LB - LB3;
+
+    __shared__ uint64_t s_keys[2][CAP3];
+    __shared__ uint32_t s_bin[NB3 + 1];
+    __shared__ uint32_t s_st[MAXT], s_len[MAXT];
+    __shared__ uint64_t s_tmp[NT3 / 64 + 2];
+
+    const uint32_t na = gather_sub(J.h[0], J.B2, b, d, s_keys[0], s_st, s_len, s_tmp);
+    if (SORT_OUT) {
+        if (na > CAP3) {
+            if (threadIdx.x == 0) atomicOr(J.flags, 1u);
+            return;
+        }
+        lds_sort(s_keys[0], na, sh3, s_bin, s_tmp);
+        // output position: bucket start + keys of lower digits in every tile
+        const SubRef r = sub_ref(J.h[0], b);
+        uint64_t part = 0;
+        for (uint32_t t = r.t0 + threadIdx.x; t < r.t1; t += NT3)
+            part += J.h[0].digstart[(size_t)d * J.h[0].ntile2_max + t];
+        uint64_t tot;
+        block_excl_scan<NT3>(part, s_tmp, &tot);
+        const uint64_t pos = r.pos0 + tot;
+        for (uint32_t i = threadIdx.x; i < na; i += NT3) sorted_out[pos + i] = s_keys[0][i];
+        return;
+    }
+    const uint32_t nbk = gather_sub(J.h[1], J.B2, b, d, s_keys[1], s_st, s_len, s_tmp);
+    const uint64_t s_lo = LB == 0 ? 0 : ((uint64_t)s << (64 - LB));
+    const uint64_t s_hi = LB == 0 ? ~0ull : (s_lo + ((1ull << (64 - LB)) - 1));
+    const uint64_t t_lo = J.t_lo, t_hi = J.t_hi;
+
+    if (na > CAP3 || nbk > CAP3) {
+        // over-capacity fallback: every a against every key of the (distinct)
+        // sub-buckets s-1, s, s+1 of B', straight from global memory
+        if (threadIdx.x == 0) atomicOr(J.flags, 2u);
+        uint32_t nbrs[3] = {(s + NS - 1) & (NS - 1), s, (s + 1) & (NS - 1)};
+        int nn = 3;
+        if (nbrs[0] == nbrs[2]) nn = (nbrs[0] == s) ? 1 : 2;
+        if (nn == 1) nbrs[0] = s;
+        if (nn == 2) nbrs[1] = s;
+        const HalfArgs &HA = J.h[0];
+        const SubRef ra = sub_ref(HA, b);
+        uint32_t seen = 0;
+        for (uint32_t t = ra.t0; t < ra.t1; ++t) {
+            const uint32_t st = HA.digstart[(size_t)d * HA.ntile2_max + t];
+            const uint32_t en = HA.digstart[(size_t)(d + 1) * HA.ntile2_max + t];
+            const uint64_t tb = ra.pos0 + (uint64_t)(t - ra.t0) * T2;
+            for (uint32_t q = st + threadIdx.x; q < en; q += NT3) {
+                const uint64_t a = HA.keys[tb + q];
+                for (int k = 0; k < nn; ++k) {
+                    const uint32_t ns = nbrs[k];
+                    for_each_global(J.h[1], J.B2, (int)(ns >> J.B2), (int)(ns & ((1u << J.B2) - 1)),
+                                    [&](uint64_t bk) {
+                                        if (in_win(a, bk, t_lo, t_hi)) emit_pair(J, a, bk);
+                                        return *J.kp_count <= J.kcap;
+                                    });
+                }
+                if (*J.kp_count > J.kcap) return;
+            }
+            seen += en - st;
+        }
+        (void)seen;
+        return;
+    }
+
+    lds_sort(s_keys[0], na, sh3, s_bin, s_tmp);
+    lds_sort(s_keys[1], nbk, sh3, s_bin, s_tmp);
+    const uint64_t *A = s_keys[0];
+    const uint64_t *B = s_keys[1];
+
+    // merge path: thread t owns diagonals [t*D, (t+1)*D) of the merged order
+    // (ties: A before B), so every thread walks the same number of elements.
+    const uint32_t total = na + nbk;
+    const uint32_t D = (total + NT3 - 1) / NT3;
+    const uint32_t k0 = min(total, threadIdx.x * D);
+    const uint32_t k1 = min(total, k0 + D);
+    uint32_t lo = k0 > nbk ? k0 - nbk : 0, hi = min(k0, na);
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (A[mid] <= B[k0 - mid - 1]) lo = mid + 1;
+        else hi = mid;
+    }
+    uint32_t i = lo, j = k0 - lo;
+    for (uint32_t k = k0; k < k1; ++k) {
+        if (j >= nbk || (i < na && A[i] <= B[j])) {
+            // A[i] consumed: B[0..j) < a <= B[j..]
+            const uint64_t a = A[i];
+            const uint64_t wlo = a >= t_hi ? a - t_hi : 0;
+            const uint64_t whi = a <= ~0ull - t_lo ? a + t_lo : ~0ull;
+            for (int q = (int)j - 1; q >= 0 && B[q] >= wlo; --q) emit_pair(J, a, B[q]);
+            for (uint32_t q = j; q < nbk && B[q] <= whi; ++q) emit_pair(J, a, B[q]);
+            // window reaching past this sub-bucket (or wrapping past 0)
+            const bool low_edge = (a - s_lo) < t_hi;
+            const bool high_edge = (s_hi - a) < t_lo;
+            if (low_edge || high_edge) {
+                const uint32_t nlo = (s + NS - 1) & (NS - 1), nhi = (s + 1) & (NS - 1);
+                if (low_edge) edge_scan(J, a, s, nlo, wlo, whi);
+                if (high_edge && !(low_edge && nhi == nlo)) edge_scan(J, a, s, nhi, wlo, whi);
+            }
+            ++i;
+        } else {
+            ++j;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ K4
+// Re-enumerate one half (same Gray walk as K1, no stores) and record every
+// (key, pattern) whose key occurs among the candidate key pairs.
+__global__ __launch_bounds__(NT1) void k_recover(JobArgs J) {
+    const int half = blockIdx.y;
+    const HalfArgs &H = J.h[half];
+    const uint32_t wg = blockIdx.x;
+    if (wg >= H.nwg1) return;
+    const uint64_t cnt = *J.kp_count;
+    if (cnt > J.kcap || cnt == 0) return;
+    const int tid = threadIdx.x;
+    const int nl = 1 << H.L;
+    const bool act = tid < nl;
+
+    __shared__ uint64_t s_w[64];
+    __shared__ uint32_t s_bits[RBITS / 32];
+    __shared__ uint64_t s_list[KCAP_MAX];
+    if (tid < H.m) s_w[tid] = J.wts[blockIdx.y][tid];
+    for (int i = tid; i < RBITS / 32; i += NT1) s_bits[i] = 0;
+    __syncthreads();
+    for (uint32_t i = tid; i < cnt; i += NT1) {
+        const uint64_t k = J.kp[2 * i + half];
+        s_list[i] = k;
+        const uint32_t h = (uint32_t)(k >> (64 - RBITS_LOG));
+        atomicOr(&s_bits[h >> 5], 1u << (h & 31));
+    }
+    __syncthreads();
+
+    uint64_t slo = 0;
+    for (int i = 0; i < H.L; ++i)
+        if ((tid >> i) & 1) slo += s_w[i];
+    const uint64_t h0 = (uint64_t)wg * H.spw;
+    const uint64_t h1 = min(h0 + (uint64_t)H.spw, H.steps);
+    uint64_t g = h0 ^ (h0 >> 1);
+    uint64_t shi = 0;
+    for (int i = 0; i < H.m - H.L; ++i)
+        if ((g >> i) & 1) shi += s_w[H.L + i];
+    for (uint64_t h = h0; h < h1; ++h) {
+        const uint64_t key = slo + shi;
+        if (act) {
+            const uint32_t hb = (uint32_t)(key >> (64 - RBITS_LOG));
+            if ((s_bits[hb >> 5] >> (hb & 31)) & 1) {
+                for (uint32_t i = 0; i < cnt; ++i) {
+                    if (s_list[i] == key) {
+                        const uint64_t pat = (uint64_t)tid | (g << H.L);
+                        const uint32_t r = atomicAdd(&J.rec_count[half], 1u);
+                        if (r < J.kcap) {
+                            J.rec[((size_t)half * J.kcap + r) * 2] = key;
+                            J.rec[((size_t)half * J.kcap + r) * 2 + 1] = pat;
+                        }
+                        break;
+                    }
+                }
+            }
+        }
+        const uint64_t t = h + 1;
+        if (t < h1) {
+            const int bb = __builtin_ctzll(t);
+            g ^= 1ull << bb;
+            const uint64_t wb = s_w[H.L + bb];
+            shi += ((g >> bb) & 1) ? wb : (0 - wb);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ K5
+// One workgroup: distinct key pairs x (patterns of each key) -> pattern pairs.
+__global__ __launch_bounds__(NT1) void k_pairs(JobArgs J) {
+    const uint64_t cnt = *J.kp_count;
+    __shared__ uint64_t s_total;
+    if (threadIdx.x == 0) s_total = 0;
+    __syncthreads();
+    if (cnt > J.kcap) {
+        if (threadIdx.x == 0) *J.out_count = ~0ull;
+        return;
+    }
+    const uint32_t ra = min((uint64_t)J.rec_count[0], J.kcap), rb = min((uint64_t)J.rec_count[1], J.kcap);
+    for (uint32_t p = threadIdx.x; p < cnt; p += NT1) {
+        const uint64_t a = J.kp[2 * p], bk = J.kp[2 * p + 1];
+        bool first = true;
+        for (uint32_t q = 0; q < p && first; ++q)
+            if (J.kp[2 * q] == a && J.kp[2 * q + 1] == bk) first = false;
+        if (!first) continue;
+        for (uint32_t x = 0; x < ra; ++x) {
+            if (J.rec[2 * x] != a) continue;
+            const uint64_t pa = J.rec[2 * x + 1];
+            for (uint32_t y = 0; y < rb; ++y) {
+                if (J.rec[((size_t)J.kcap + y) * 2] != bk) continue;
+                const uint64_t pb = J.rec[((size_t)J.kcap + y) * 2 + 1];
+                if (pa == 0 && pb == 0) continue;  // the empty pattern s = 0
+                const unsigned long long o = atomicAdd((unsigned long long *)&s_total, 1ull);
+                if (o < J.cap) {
+                    J.out[2 * o] = pa;
+                    J.out[2 * o + 1] = pb;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *J.out_count = s_total > J.cap ? ~0ull : s_total;
+}
+
+}  // namespace dev
+
+// ======================================================================
+// host side: plans and enqueue
+// ======================================================================
+using namespace dev;
+
+static inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+
+static void plan_half(int m, HalfPlan &h) {
+    h.m = m;
+    h.L = m < 8 ? m : 8;
+    h.N = 1ull << m;
+    h.steps = 1ull << (m - h.L);
+    h.spw = (uint32_t)(KPT1 * TILES1);
+    h.nwg1 = (uint32_t)((h.steps + h.spw - 1) / h.spw);
+}
+
+static void plan_bits(uint64_t nmax, int &B1, int &B2) {
+    int lg = 0;
+    while ((1ull << lg) < nmax) ++lg;
+    int LB = lg > 10 ? lg - 10 : 0;
+    if (LB <= 16) {
+        B1 = LB < 8 ? LB : 8;
+        B2 = LB - B1;
+    } else {
+        B1 = (LB + 1) / 2;
+        B2 = LB / 2;
+    }
+    if (B1 > MAXB1_LOG) {
+        B2 += B1 - MAXB1_LOG;
+        B1 = MAXB1_LOG;
+    }
+    if (B2 > MAXB2_LOG) B2 = MAXB2_LOG;
+}
+
+// Carve the workspace; returns bytes needed.  With base == nullptr only sizes.
+static uint64_t layout(JobPlan &P, char *base) {
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        uint64_t o = off;
+        off = align_up(off + bytes, 256);
+        return base ? (void *)(base + o) : nullptr;
+    };
+    const int nb = 1 << P.B1, nd = 1 << P.B2;
+    for (int k = 0; k < P.nhalves; ++k) {
+        HalfPlan &h = P.h[k];
+        h.ntile2_max = (uint32_t)(h.N / T2 + nb + 1);
+        h.a.keys = (uint64_t *)take(h.N * 8);
+        h.a.hist1 = (uint64_t *)take((uint64_t)nb * h.nwg1 * 8);
+        h.a.bstart = (uint64_t *)take((uint64_t)(nb + 1) * 8);
+        h.a.tstart = (uint32_t *)take((uint64_t)(nb + 1) * 4);
+        h.a.digstart = (uint16_t *)take((uint64_t)(nd + 1) * h.ntile2_max * 2);
+        h.a.N = h.N;
+        h.a.steps = h.steps;
+        h.a.spw = h.spw;
+        h.a.nwg1 = h.nwg1;
+        h.a.ntile2_max = h.ntile2_max;
+        h.a.m = h.m;
+        h.a.L = h.L;
+    }
+    P.kp = (uint64_t *)take(KCAP_MAX * 16);
+    P.rec = (uint64_t *)take(2ull * KCAP_MAX * 16);
+    P.counters = (uint64_t *)take(64);
+    return off;
+}
+
+uint64_t plan_job(int na, int nb, JobPlan &P) {
+    P = JobPlan();
+    P.nhalves = nb >= 0 ? 2 : 1;
+    plan_half(na, P.h[0]);
+    uint64_t nmax = P.h[0].N;
+    if (nb >= 0) {
+        plan_half(nb, P.h[1]);
+        nmax = std::max(nmax, P.h[1].N);
+    }
+    plan_bits(nmax, P.B1, P.B2);
+    return layout(P, nullptr);
+}
+
+static void enqueue_common(JobPlan &P, char *ws, const uint64_t *wa, const uint64_t *wb, JobArgs &J) {
+    layout(P, ws);
+    J = JobArgs();
+    J.B1 = P.B1;
+    J.B2 = P.B2;
+    for (int k = 0; k < 2; ++k) J.h[k] = P.h[k < P.nhalves ? k : 0].a;
+    for (int i = 0; i < P.h[0].m; ++i) J.wts[0][i] = wa[i];
+    if (P.nhalves == 2)
+        for (int i = 0; i < P.h[1].m; ++i) J.wts[1][i] = wb[i];
+    else
+        for (int i = 0; i < P.h[0].m; ++i) J.wts[1][i] = wa[i];
+    J.kp = P.kp;
+    J.kp_count = P.counters;
+    J.rec = P.rec;
+    J.rec_count = (uint32_t *)(P.counters + 1);
+    J.flags = (uint32_t *)(P.counters + 2);
+}
+
+static hipError_t launch_front(JobPlan &P, JobArgs &J, hipStream_t st, StageEvents *ev) {
+    const int nh = P.nhalves;
+    uint32_t mw = 0;
+    uint64_t mt = 0;
+    for (int k = 0; k < nh; ++k) {
+        mw = std::max(mw, P.h[k].nwg1);
+        mt = std::max<uint64_t>(mt, P.h[k].ntile2_max);
+    }
+    auto rec = [&](int i) {
+        if (ev && ev->ev[i]) (void)hipEventRecord((hipEvent_t)ev->ev[i], st);
+    };
+    rec(0);
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, J);
+    hipLaunchKernelGGL(k_enum<true>, dim3(mw, nh), dim3(NT1), 0, st, J);
+    rec(1);
+    hipLaunchKernelGGL(k_scan_cols, dim3(1 << P.B1, nh), dim3(NT1), 0, st, J);
+    hipLaunchKernelGGL(k_scan_buckets, dim3(1, nh), dim3(NT1), 0, st, J);
+    rec(2);
+    hipLaunchKernelGGL(k_enum<false>, dim3(mw, nh), dim3(NT1), 0, st, J);
+    rec(3);
+    hipLaunchKernelGGL(k_tile2, dim3((uint32_t)mt, nh), dim3(NT2), 0, st, J);
+    rec(4);
+    return hipGetLastError();
+}
+
+rfr_status enqueue_recombine(const uint64_t *w, int n, uint64_t t_lo, uint64_t t_hi, void *ws,
+                             size_t ws_bytes, hipStream_t st, uint64_t *cand, uint64_t cap,
+                             uint64_t *count, StageEvents *ev, std::string &err) {
+    if (!w || n < 2 || n > 2 * MAX_HALF + 1 || !ws || !cand || !count) {
+        err = "rfr_recombine_dev: bad argument (need 2 <= n <= 69 and non-NULL buffers)";
+        return RFR_EINVAL;
+    }
+    if (t_lo >= (1ull << 32) || t_hi >= (1ull << 32) || t_lo + t_hi >= (1ull << 32)) {
+        err = "rfr_recombine_dev: window must satisfy t_lo + t_hi < 2^32";
+        return RFR_EINVAL;
+    }
+    int na, nb;
+    split_halves(n, na, nb);
+    JobPlan P;
+    uint64_t need = plan_job(na, nb, P);
+    if (ws_bytes < need) {
+        err = "rfr_recombine_dev: workspace too small";
+        return RFR_ENOMEM;
+    }
+    JobArgs J;
+    std::vector<uint64_t> wneg(nb);
+    for (int i = 0; i < nb; ++i) wneg[i] = 0 - w[na + i];
+    enqueue_common(P, (char *)ws, w, wneg.data(), J);
+    J.t_lo = t_lo;
+    J.t_hi = t_hi;
+    J.kcap = std::min<uint64_t>(cap + 1, KCAP_MAX);
+    J.out = cand;
+    J.out_count = count;
+    J.cap = cap;
+    if (launch_front(P, J, st, ev) != hipSuccess) {
+        err = "kernel launch failed";
+        return RFR_EDEVICE;
+    }
+    hipLaunchKernelGGL(k_join<false>, dim3(1u << (P.B1 + P.B2)), dim3(NT3), 0, st, J, (uint64_t *)nullptr);
+    if (ev && ev->ev[5]) (void)hipEventRecord((hipEvent_t)ev->ev[5], st);
+    uint32_t mw = std::max(P.h[0].nwg1, P.h[1].nwg1);
+    hipLaunchKernelGGL(k_recover, dim3(mw, 2), dim3(NT1), 0, st, J);
+    hipLaunchKernelGGL(k_pairs, dim3(1), dim3(NT1), 0, st, J);
+    if (ev && ev->ev[6]) (void)hipEventRecord((hipEvent_t)ev->ev[6], st);
+    if (hipGetLastError() != hipSuccess) {
+        err = "kernel launch failed";
+        return RFR_EDEVICE;
+    }
+    return RFR_OK;
+}
+
+size_t recombine_workspace(int n) {
+    if (n < 2 || n > 2 * MAX_HALF + 1) return 0;
+    int na, nb;
+    split_halves(n, na, nb);
+    JobPlan P;
+    return plan_job(na, nb, P);
+}
+
+size_t expand_workspace(int m) {
+    if (m < 1 || m > 30) return 0;
+    JobPlan P;
+    return plan_job(m, -1, P);
+}
+
+rfr_status enqueue_expand(const uint64_t *w, int m, int negate, void *ws, size_t ws_bytes,
+                          hipStream_t st, uint64_t *sorted, std::string &err) {
+    if (!w || m < 1 || m > 30 || !ws || !sorted) {
+        err = "rfr_expand_dev: bad argument (need 1 <= m <= 30)";
+        return RFR_EINVAL;
+    }
+    JobPlan P;
+    uint64_t need = plan_job(m, -1, P);
+    if (ws_bytes < need) {
+        err = "rfr_expand_dev: workspace too small";
+        return RFR_ENOMEM;
+    }
+    std::vector<uint64_t> ww(w, w + m);
+    if (negate)
+        for (auto &v : ww) v = 0 - v;
+    JobArgs J;
+    enqueue_common(P, (char *)ws, ww.data(), nullptr, J);
+    J.kcap = 1;
+    if (launch_front(P, J, st, nullptr) != hipSuccess) {
+        err = "kernel launch failed";
+        return RFR_EDEVICE;
+    }
+    hipLaunchKernelGGL(k_join<true>, dim3(1u << (P.B1 + P.B2)), dim3(NT3), 0, st, J, sorted);
+    if (hipGetLastError() != hipSuccess) {
+        err = "kernel launch failed";
+        return RFR_EDEVICE;
+    }
+    return RFR_OK;
+}
+
+}  // namespace rfr

@@ -1,0 +1,729 @@
+// Host core of the RFR library: normalisation, roots, elements, weights, window,
+// confirmation and atoms.  Plain C++17, no device code; compiled without
+// floating-point contraction so the error-free transformations stay exact.
+//
+// Paper: Iravanian, arXiv 2410.15880.
+//   Section 2     preconditions (square-free, monic transform), Eq 1 real
+//                 factorisation, the element set R, Algorithm FACTOR.
+//   Section 3.3   integer weights rho_hat = floor(rho * M), Eq 18, accept Eq 19.
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <map>
+#include <numeric>
+
+#include "rfr_internal.h"
+
+namespace rfr {
+
+// ======================================================================
+// double-double arithmetic (error-free transformations, Dekker / Knuth)
+// ======================================================================
+static inline dd two_sum(double a, double b) {
+    double s = a + b;
+    double bb = s - a;
+    double e = (a - (s - bb)) + (b - bb);
+    return {s, e};
+}
+static inline dd quick_two_sum(double a, double b) {
+    double s = a + b;
+    return {s, b - (s - a)};
+}
+static inline dd two_prod(double a, double b) {
+    double p = a * b;
+    return {p, std::fma(a, b, -p)};
+}
+static inline dd mkdd(double x) { return {x, 0.0}; }
+static inline dd dd_from_i64(int64_t v) {
+    // top has at most 52 significant bits (exact in a double), rest < 2^11
+    int64_t top = v & ~(int64_t)0x7FF;
+    int64_t rest = v - top;
+    return two_sum((double)top, (double)rest);
+}
+static inline dd operator+(dd a, dd b) {
+    dd s = two_sum(a.hi, b.hi);
+    dd t = two_sum(a.lo, b.lo);
+    s.lo += t.hi;
+    s = quick_two_sum(s.hi, s.lo);
+    s.lo += t.lo;
+    return quick_two_sum(s.hi, s.lo);
+}
+static inline dd operator-(dd a) { return {-a.hi, -a.lo}; }
+static inline dd operator-(dd a, dd b) { return a + (-b); }
+static inline dd operator*(dd a, dd b) {
+    dd p = two_prod(a.hi, b.hi);
+    p.lo += a.hi * b.lo + a.lo * b.hi;
+    return quick_two_sum(p.hi, p.lo);
+}
+static inline dd operator*(dd a, double b) {
+    dd p = two_prod(a.hi, b);
+    p.lo += a.lo * b;
+    return quick_two_sum(p.hi, p.lo);
+}
+static inline dd operator/(dd a, dd b) {
+    double q1 = a.hi / b.hi;
+    dd r = a - b * q1;
+    double q2 = r.hi / b.hi;
+    r = r - b * q2;
+    double q3 = r.hi / b.hi;
+    dd q = quick_two_sum(q1, q2);
+    return q + mkdd(q3);
+}
+static inline double to_d(dd a) { return a.hi + a.lo; }
+static inline dd dd_abs(dd a) { return a.hi < 0 ? -a : a; }
+
+static inline cdd operator+(cdd a, cdd b) { return {a.re + b.re, a.im + b.im}; }
+static inline cdd operator-(cdd a, cdd b) { return {a.re - b.re, a.im - b.im}; }
+static inline cdd operator*(cdd a, cdd b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+static inline cdd operator/(cdd a, cdd b) {
+    dd den = b.re * b.re + b.im * b.im;
+    return {(a.re * b.re + a.im * b.im) / den, (a.im * b.re - a.re * b.im) / den};
+}
+static inline double cabs_d(cdd a) { return std::hypot(to_d(a.re), to_d(a.im)); }
+
+// ======================================================================
+// normalisation (Section 2 preconditions)
+// ======================================================================
+static int64_t gcd64(int64_t a, int64_t b) {
+    a = a < 0 ? -a : a;
+    b = b < 0 ? -b : b;
+    while (b) {
+        int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+rfr_status normalise(const int64_t *coeffs, int degree, Prepared &P, std::string &err) {
+    if (!coeffs || degree < 1 || degree > RFR_MAX_DEGREE) {
+        err = "degree must be in [1, RFR_MAX_DEGREE] and coeffs non-NULL";
+        return RFR_EINVAL;
+    }
+    if (coeffs[degree] == 0) {
+        err = "leading coefficient is zero";
+        return RFR_EINVAL;
+    }
+    for (int i = 0; i <= degree; ++i) {
+        if (coeffs[i] == INT64_MIN) {
+            err = "coefficient INT64_MIN is not supported";
+            return RFR_EOVERFLOW;
+        }
+    }
+    int k = 0;
+    while (coeffs[k] == 0) ++k;
+    if (k > 1) {
+        err = "x^2 divides p: not square-free";
+        return RFR_ENOTSQFREE;
+    }
+    int64_t g = 0;
+    for (int i = k; i <= degree; ++i) g = gcd64(g, coeffs[i]);
+    if (coeffs[degree] < 0) g = -g;
+    P.content = g;
+    P.xpow = k;
+    P.prim.assign(coeffs + k, coeffs + degree + 1);
+    for (auto &c : P.prim) c /= g;
+    return RFR_OK;
+}
+
+// ======================================================================
+// modular square-free test (used only to classify a root-separation failure)
+// ======================================================================
+static uint64_t mulmod(uint64_t a, uint64_t b, uint64_t q) {
+    return (uint64_t)((unsigned __int128)a * b % q);
+}
+static uint64_t powmod(uint64_t a, uint64_t e, uint64_t q) {
+    uint64_t r = 1;
+    while (e) {
+        if (e & 1) r = mulmod(r, a, q);
+        a = mulmod(a, a, q);
+        e >>= 1;
+    }
+    return r;
+}
+static int gcd_degree_mod(const std::vector<int64_t> &p, uint64_t q) {
+    auto red = [&](int64_t v) { int64_t m = v % (int64_t)q; return (uint64_t)(m < 0 ? m + (int64_t)q : m); };
+    std::vector<uint64_t> a(p.size()), b(p.size() - 1);
+    for (size_t i = 0; i < p.size(); ++i) a[i] = red(p[i]);
+    for (size_t i = 1; i < p.size(); ++i) b[i - 1] = mulmod(red(p[i]), (uint64_t)i % q, q);
+    auto trim = [](std::vector<uint64_t> &v) { while (!v.empty() && v.back() == 0) v.pop_back(); };
+    trim(a);
+    trim(b);
+    while (!b.empty()) {
+        // a = a mod b
+        uint64_t inv = powmod(b.back(), q - 2, q);
+        while (a.size() >= b.size() && !a.empty()) {
+            uint64_t f = mulmod(a.back(), inv, q);
+            size_t sh = a.size() - b.size();
+            for (size_t i = 0; i < b.size(); ++i)
+                a[sh + i] = (a[sh + i] + q - mulmod(f, b[i], q)) % q;
+            trim(a);
+        }
+        std::swap(a, b);
+    }
+    return a.empty() ? -1 : (int)a.size() - 1;
+}
+static bool probably_not_squarefree(const std::vector<int64_t> &p) {
+    const uint64_t primes[3] = {2305843009213693951ull, 1152921504606846883ull, 576460752303423433ull};
+    for (uint64_t q : primes) {
+        if (gcd_degree_mod(p, q) <= 0) return false;  // certified square-free mod q
+    }
+    return true;
+}
+
+// ======================================================================
+// roots: FP64 Aberth-Ehrlich, then double-double Newton polish
+// ======================================================================
+using cplx = std::complex<double>;
+
+// p(z)/p'(z) in FP64; for |z| > 1 through the reversed polynomial.
+static cplx newton_ratio(const std::vector<double> &a, cplx z) {
+    int d = (int)a.size() - 1;
+    if (std::abs(z) <= 1.0) {
+        cplx p = a[d], dp = 0;
+        for (int i = d - 1; i >= 0; --i) {
+            dp = dp * z + p;
+            p = p * z + a[i];
+        }
+        return p / dp;
+    }
+    cplx y = 1.0 / z;
+    cplx q = a[0], dq = 0;
+    for (int i = 1; i <= d; ++i) {
+        dq = dq * y + q;
+        q = q * y + a[i];
+    }
+    return z * q / ((double)d * q - y * dq);
+}
+
+// Initial approximations on circles from the upper convex hull of
+// (i, log|a_i|) (the Newton polygon), one circle per hull edge.
+static std::vector<cplx> initial_points(const std::vector<double> &a) {
+    int d = (int)a.size() - 1;
+    std::vector<int> idx;
+    std::vector<double> lg;
+    for (int i = 0; i <= d; ++i)
+        if (a[i] != 0) {
+            idx.push_back(i);
+            lg.push_back(std::log(std::fabs(a[i])));
+        }
+    std::vector<int> hull;  // indices into idx
+    for (int k = 0; k < (int)idx.size(); ++k) {
+        while (hull.size() >= 2) {
+            int i1 = hull[hull.size() - 2], i2 = hull.back();
+            double x1 = idx[i1], y1 = lg[i1], x2 = idx[i2], y2 = lg[i2], x3 = idx[k], y3 = lg[k];
+            if ((x2 - x1) * (y3 - y1) - (y2 - y1) * (x3 - x1) >= 0) hull.pop_back();
+            else break;
+        }
+        hull.push_back(k);
+    }
+    std::vector<cplx> z;
+    const double two_pi = 6.283185307179586;
+    for (size_t h = 0; h + 1 < hull.size(); ++h) {
+        int k = idx[hull[h]], l = idx[hull[h + 1]];
+        double u = std::exp((lg[hull[h]] - lg[hull[h + 1]]) / (l - k));
+        for (int j = 0; j < l - k; ++j) {
+            double ang = two_pi * j / (l - k) + two_pi * k / d + 0.4;
+            z.push_back(std::polar(u, ang));
+        }
+    }
+    return z;
+}
+
+static void aberth(const std::vector<double> &a, std::vector<cplx> &z, int maxit) {
+    int d = (int)a.size() - 1;
+    std::vector<char> done(d, 0);
+    for (int it = 0; it < maxit; ++it) {
+        int active = 0;
+        for (int i = 0; i < d; ++i) {
+            if (done[i]) continue;
+            cplx N = newton_ratio(a, z[i]);
+            cplx S = 0;
+            for (int j = 0; j < d; ++j)
+                if (j != i) S += 1.0 / (z[i] - z[j]);
+            cplx wc = N / (1.0 - N * S);
+            if (!std::isfinite(wc.real()) || !std::isfinite(wc.imag())) {
+                done[i] = 1;
+                continue;
+            }
+            z[i] -= wc;
+            if (std::abs(wc) <= 1e-15 * std::max(std::abs(z[i]), 1e-300)) done[i] = 1;
+            else ++active;
+        }
+        if (!active) break;
+    }
+}
+
+// Complex double-double Horner: p(z), p'(z) and a bound on the rounding error
+// of p(z) (and of p'(z)).
+struct Eval {
+    cdd p, dp;
+    double err_p, err_dp;
+};
+static Eval eval_cdd(const std::vector<dd> &a, const cdd &z) {
+    int d = (int)a.size() - 1;
+    cdd p{a[d], mkdd(0)}, dp{mkdd(0), mkdd(0)};
+    double az = cabs_d(z), s = std::fabs(to_d(a[d])), ds = 0;
+    for (int i = d - 1; i >= 0; --i) {
+        dp = dp * z + p;
+        p = p * z + cdd{a[i], mkdd(0)};
+        ds = ds * az + s;
+        s = s * az + std::fabs(to_d(a[i]));
+    }
+    // each complex dd multiply-add has relative error below ~16 * 2^-104;
+    // Horner accumulates at most 2d of them
+    const double u = 16.0 * std::ldexp(1.0, -104);
+    return {p, dp, 2.0 * d * u * s * 1.01, 2.0 * d * u * ds * 1.01};
+}
+static Eval eval_rdd(const std::vector<dd> &a, const dd &x) {
+    int d = (int)a.size() - 1;
+    dd p = a[d], dp = mkdd(0);
+    double ax = std::fabs(to_d(x)), s = std::fabs(to_d(a[d])), ds = 0;
+    for (int i = d - 1; i >= 0; --i) {
+        dp = dp * x + p;
+        p = p * x + a[i];
+        ds = ds * ax + s;
+        s = s * ax + std::fabs(to_d(a[i]));
+    }
+    const double u = 8.0 * std::ldexp(1.0, -104);
+    return {{p, mkdd(0)}, {dp, mkdd(0)}, 2.0 * d * u * s * 1.01, 2.0 * d * u * ds * 1.01};
+}
+
+// Newton inclusion radius: a root lies within d |p(z)| / |p'(z)|.
+static double radius_of(const Eval &e, int d) {
+    double ap = cabs_d(e.p) + e.err_p;
+    double adp = cabs_d(e.dp) - e.err_dp;
+    if (!(adp > 0)) return INFINITY;
+    return d * ap / adp * (1.0 + 1e-12);
+}
+
+static cdd polish_c(const std::vector<dd> &a, cdd z, int iters) {
+    for (int k = 0; k < iters; ++k) {
+        Eval e = eval_cdd(a, z);
+        if (cabs_d(e.dp) == 0) break;
+        cdd step = e.p / e.dp;
+        z = z - step;
+        if (cabs_d(step) <= 1e-31 * std::max(cabs_d(z), 1e-300)) break;
+    }
+    return z;
+}
+static dd polish_r(const std::vector<dd> &a, dd x, int iters) {
+    for (int k = 0; k < iters; ++k) {
+        Eval e = eval_rdd(a, x);
+        if (to_d(e.dp.re) == 0) break;
+        dd step = e.p.re / e.dp.re;
+        x = x - step;
+        if (std::fabs(to_d(step)) <= 1e-31 * std::max(std::fabs(to_d(x)), 1e-300)) break;
+    }
+    return x;
+}
+
+struct Disc {
+    cplx c;
+    double r;
+};
+static bool discs_disjoint(const std::vector<Disc> &D) {
+    // sort by real part and sweep
+    std::vector<int> o(D.size());
+    std::iota(o.begin(), o.end(), 0);
+    std::sort(o.begin(), o.end(), [&](int i, int j) { return D[i].c.real() - D[i].r < D[j].c.real() - D[j].r; });
+    double rmax = 0;
+    for (auto &x : D) rmax = std::max(rmax, x.r);
+    for (size_t ii = 0; ii < o.size(); ++ii) {
+        const Disc &A = D[o[ii]];
+        for (size_t jj = ii + 1; jj < o.size(); ++jj) {
+            const Disc &B = D[o[jj]];
+            if (B.c.real() - B.r > A.c.real() + A.r + 2 * rmax) break;
+            // compare with a small relative margin for the FP64 distance
+            double dist = std::abs(A.c - B.c);
+            if (dist * (1 - 1e-12) <= A.r + B.r) return false;
+        }
+    }
+    return true;
+}
+
+static void fail_roots(const Prepared &P, rfr_status &st, std::string &err, const char *why) {
+    if (probably_not_squarefree(P.prim)) {
+        st = RFR_ENOTSQFREE;
+        err = "p has a repeated factor (gcd(p, p') non-trivial)";
+    } else {
+        st = RFR_EPRECISION;
+        err = why;
+    }
+}
+
+// ======================================================================
+// elements, weights, window (Section 2, Section 3.3 Eq 18-19)
+// ======================================================================
+
+// floor(frac(v) * 2^64) mod 2^64 for a double-double v, |v| < 2^60.
+static uint64_t weight_of(dd v) {
+    double fl = std::floor(v.hi);
+    dd f = two_sum(v.hi - fl, v.lo);  // v.hi - fl is exact
+    f = quick_two_sum(f.hi, f.lo);
+    while (f.hi < 0) f = f + mkdd(1.0);
+    while (f.hi >= 1.0) f = f - mkdd(1.0);
+    // f in [0,1) as hi + lo; scale by 2^64 exactly
+    double H = std::ldexp(f.hi, 64), L = std::ldexp(f.lo, 64);
+    double h0 = std::floor(H);
+    double rem = (H - h0) + L;
+    double fr = std::floor(rem);
+    uint64_t hi_int = h0 >= 18446744073709551616.0 ? 0 : (uint64_t)h0;
+    return hi_int + (uint64_t)(int64_t)fr;
+}
+
+rfr_status prepare_elements(Prepared &P, std::string &err) {
+    const int d = (int)P.prim.size() - 1;
+    P.reals.clear();
+    P.pairs.clear();
+    P.w.clear();
+    if (d < 1) {
+        P.n = P.r = 0;
+        return RFR_OK;
+    }
+    std::vector<double> ad(d + 1);
+    std::vector<dd> add(d + 1);
+    for (int i = 0; i <= d; ++i) {
+        ad[i] = (double)P.prim[i];
+        add[i] = dd_from_i64(P.prim[i]);
+    }
+    std::vector<cplx> z;
+    if (d == 1) {
+        z = {cplx(-ad[0] / ad[1], 0)};
+    } else {
+        z = initial_points(ad);
+        aberth(ad, z, 400);
+    }
+    // polish every root in complex double-double and take its inclusion disc
+    std::vector<cdd> zc(d);
+    std::vector<Disc> D(d);
+    for (int i = 0; i < d; ++i) {
+        cdd c{mkdd(z[i].real()), mkdd(z[i].imag())};
+        c = polish_c(add, c, 6);
+        Eval e = eval_cdd(add, c);
+        zc[i] = c;
+        D[i] = {cplx(to_d(c.re), to_d(c.im)), radius_of(e, d)};
+    }
+    rfr_status st = RFR_OK;
+    if (!discs_disjoint(D)) {
+        fail_roots(P, st, err, "root inclusion discs overlap (roots not separated)");
+        return st;
+    }
+    // classify: a disc meeting the real axis is re-centred on it and polished in R
+    std::vector<dd> reals;
+    std::vector<double> rr;
+    std::vector<cdd> up, down;
+    std::vector<double> rup, rdown;
+    std::vector<Disc> F;
+    for (int i = 0; i < d; ++i) {
+        if (std::fabs(D[i].c.imag()) <= D[i].r) {
+            dd x = polish_r(add, zc[i].re, 6);
+            Eval e = eval_rdd(add, x);
+            double rx = radius_of(e, d);
+            reals.push_back(x);
+            rr.push_back(rx);
+            F.push_back({cplx(to_d(x), 0), rx});
+        } else {
+            (D[i].c.imag() > 0 ? up : down).push_back(zc[i]);
+            (D[i].c.imag() > 0 ? rup : rdown).push_back(D[i].r);
+            F.push_back(D[i]);
+        }
+    }
+    // the final discs must again be disjoint: one root each, and a disc centred
+    // on the real axis then holds a real root
+    if (!discs_disjoint(F)) {
+        fail_roots(P, st, err, "root inclusion discs overlap after real classification");
+        return st;
+    }
+    if (up.size() != down.size()) {
+        err = "conjugate pairing failed";
+        return RFR_EPRECISION;
+    }
+    std::vector<double> rpair(up.size());
+    std::vector<char> used(down.size(), 0);
+    for (size_t i = 0; i < up.size(); ++i) {
+        cplx cz(to_d(up[i].re), -to_d(up[i].im));
+        int best = -1;
+        for (size_t j = 0; j < down.size(); ++j) {
+            if (used[j]) continue;
+            cplx w(to_d(down[j].re), to_d(down[j].im));
+            if (std::abs(cz - w) <= rup[i] + rdown[j]) {
+                if (best >= 0) {
+                    err = "ambiguous conjugate pairing";
+                    return RFR_EPRECISION;
+                }
+                best = (int)j;
+            }
+        }
+        if (best < 0) {
+            err = "conjugate pairing failed";
+            return RFR_EPRECISION;
+        }
+        used[best] = 1;
+        rpair[i] = std::max(rup[i], rdown[best]);
+    }
+    // canonical order: reals ascending, pairs by (Re, Im)
+    std::vector<int> orr(reals.size()), op(up.size());
+    std::iota(orr.begin(), orr.end(), 0);
+    std::iota(op.begin(), op.end(), 0);
+    std::sort(orr.begin(), orr.end(), [&](int i, int j) {
+        return reals[i].hi != reals[j].hi ? reals[i].hi < reals[j].hi : reals[i].lo < reals[j].lo;
+    });
+    std::sort(op.begin(), op.end(), [&](int i, int j) {
+        double ri = to_d(up[i].re), rj = to_d(up[j].re);
+        if (ri != rj) return ri < rj;
+        return to_d(up[i].im) < to_d(up[j].im);
+    });
+    P.r = (int)reals.size();
+    P.n = P.r + (int)up.size();
+    if (P.n > RFR_MAX_ELEMENTS) {
+        err = "too many elements";
+        return RFR_EOVERFLOW;
+    }
+    const dd a_d = dd_from_i64(P.prim[d]);
+    const double abs_ad = std::fabs((double)P.prim[d]);
+    double sum_delta = 0, sum_tau = 0;
+    for (int k : orr) {
+        P.reals.push_back(reals[k]);
+        dd tau = a_d * reals[k];
+        P.w.push_back(weight_of(tau));
+        sum_delta += abs_ad * rr[k];
+        sum_tau += std::fabs(to_d(tau));
+    }
+    for (int k : op) {
+        P.pairs.push_back(up[k]);
+        dd t = up[k].re * 2.0;
+        dd tau = a_d * t;
+        P.w.push_back(weight_of(tau));
+        sum_delta += abs_ad * 2.0 * rpair[k];
+        sum_tau += std::fabs(to_d(tau));
+    }
+    // Window (reading of Eq 19): a true k-element subset lands in (-k - E, E]
+    // mod 2^64 with E >= 2^64 * sum |a_d| delta_i; add the dd rounding of a_d t_i
+    // and one unit per weight for the floor of a rounded value.
+    double Ed = std::ldexp(2.0 * sum_delta + sum_tau * std::ldexp(1.0, -100), 64);
+    if (!(Ed < std::ldexp(1.0, 31))) {
+        err = "accept window too wide (roots not precise enough)";
+        return RFR_EPRECISION;
+    }
+    uint64_t E = (uint64_t)std::ceil(Ed) + 2 * (uint64_t)P.n + 2;
+    P.t_lo = (uint64_t)P.n + E;
+    P.t_hi = E;
+    return RFR_OK;
+}
+
+rfr_status prepare(const int64_t *coeffs, int degree, Prepared &P, std::string &err) {
+    rfr_status st = normalise(coeffs, degree, P, err);
+    if (st != RFR_OK) return st;
+    return prepare_elements(P, err);
+}
+
+// ======================================================================
+// confirmation (Algorithm FACTOR: keep candidates q in Z[x]) and atoms
+// ======================================================================
+using i128 = __int128;
+
+static bool round_dd(dd v, int64_t &out) {
+    if (!(std::fabs(v.hi) < 4.0e18)) return false;
+    double r = std::nearbyint(v.hi);
+    double fr = (v.hi - r) + v.lo;
+    double adj = std::nearbyint(fr);
+    fr -= adj;
+    if (std::fabs(fr) > 0.25) return false;
+    out = (int64_t)r + (int64_t)adj;
+    return true;
+}
+
+// Exact division p / f in Z[x] (f primitive); false if f does not divide p.
+// Sets overflow if an intermediate leaves the int128 range.
+static bool exact_div(const std::vector<int64_t> &p, const std::vector<int64_t> &f,
+                      std::vector<int64_t> &q, bool &overflow) {
+    int dp = (int)p.size() - 1, df = (int)f.size() - 1;
+    overflow = false;
+    if (df > dp) return false;
+    std::vector<i128> rem(p.begin(), p.end());
+    q.assign(dp - df + 1, 0);
+    const i128 lf = f[df];
+    const i128 lim = (i128)1 << 120;
+    for (int k = dp - df; k >= 0; --k) {
+        i128 lead = rem[k + df];
+        if (lead % lf != 0) return false;
+        i128 qk = lead / lf;
+        if (qk > (i128)INT64_MAX || qk < -(i128)INT64_MAX) {
+            overflow = true;
+            return false;
+        }
+        q[k] = (int64_t)qk;
+        if (qk == 0) continue;
+        for (int i = 0; i <= df; ++i) {
+            rem[k + i] -= qk * (i128)f[i];
+            if (rem[k + i] > lim || rem[k + i] < -lim) {
+                overflow = true;
+                return false;
+            }
+        }
+    }
+    for (int i = 0; i < df; ++i)
+        if (rem[i] != 0) return false;
+    return true;
+}
+
+static void make_primitive(std::vector<int64_t> &f) {
+    int64_t g = 0;
+    for (auto c : f) g = gcd64(g, c);
+    if (g == 0) return;
+    if (f.back() < 0) g = -g;
+    for (auto &c : f) c /= g;
+}
+
+static bool canon_less(const std::vector<int64_t> &a, const std::vector<int64_t> &b) {
+    if (a.size() != b.size()) return a.size() < b.size();
+    return a < b;
+}
+
+void trivial_factor(const Prepared &P, Factored &out) {
+    out.content = P.content;
+    out.factors.clear();
+    if (P.xpow == 1) out.factors.push_back({0, 1});
+    if (P.prim.size() > 1) out.factors.push_back(P.prim);
+    std::sort(out.factors.begin(), out.factors.end(), canon_less);
+}
+
+// Is sum over the side of tau^k (k = 2, 3) an integer within tolerance?  These
+// are traces of the monic-transform factor, integers for every true factor
+// (Section 2: q in Z[x] iff all its traces are integers).
+static bool traces_integral(const Prepared &P, const Pat &side) {
+    const int d = (int)P.prim.size() - 1;
+    dd a_d = dd_from_i64(P.prim[d]);
+    dd t2 = mkdd(0), t3 = mkdd(0);
+    for (int i = 0; i < P.n; ++i) {
+        if (!side.get(i)) continue;
+        if (i < P.r) {
+            dd u = a_d * P.reals[i];
+            dd u2 = u * u;
+            t2 = t2 + u2;
+            t3 = t3 + u2 * u;
+        } else {
+            const cdd &z = P.pairs[i - P.r];
+            cdd s{a_d * z.re, a_d * z.im};
+            cdd s2 = s * s;
+            cdd s3 = s2 * s;
+            t2 = t2 + s2.re * 2.0;
+            t3 = t3 + s3.re * 2.0;
+        }
+    }
+    auto near_int = [](dd v, double lim) {
+        if (!(std::fabs(v.hi) < lim)) return true;  // too large to decide: do not filter
+        double r = std::nearbyint(v.hi);
+        double fr = (v.hi - r) + v.lo;
+        fr -= std::nearbyint(fr);
+        return std::fabs(fr) <= 1e-3;
+    };
+    return near_int(t2, 1e24) && near_int(t3, 1e21);
+}
+
+rfr_status confirm_and_factor(const Prepared &P, const std::vector<Pat> &cands, Factored &out,
+                              std::string &err) {
+    const int n = P.n;
+    const int d = (int)P.prim.size() - 1;
+    const Pat full = Pat::full(n);
+    std::map<Pat, std::vector<int64_t>> found;
+    out.n_candidates = cands.size();
+    out.n_confirmed = 0;
+    auto deg_of = [&](const Pat &s) {
+        int e = 0;
+        for (int i = 0; i < n; ++i)
+            if (s.get(i)) e += i < P.r ? 1 : 2;
+        return e;
+    };
+    const dd a_d = dd_from_i64(P.prim[d]);
+    for (const Pat &s0 : cands) {
+        if (s0.empty()) continue;
+        Pat comp = full & ~s0;
+        if (found.count(s0)) continue;
+        bool small_is_s = deg_of(s0) <= deg_of(comp);
+        const Pat &side = small_is_s ? s0 : comp;
+        if (!traces_integral(P, side)) continue;
+        // a_d * prod over the side, in double-double
+        std::vector<dd> q{a_d};
+        for (int i = 0; i < n; ++i) {
+            if (!side.get(i)) continue;
+            std::vector<dd> nq(q.size() + (i < P.r ? 1 : 2), mkdd(0));
+            if (i < P.r) {
+                dd u = P.reals[i];
+                for (size_t k = 0; k < q.size(); ++k) {
+                    nq[k + 1] = nq[k + 1] + q[k];
+                    nq[k] = nq[k] - q[k] * u;
+                }
+            } else {
+                const cdd &z = P.pairs[i - P.r];
+                dd t = z.re * 2.0;
+                dd s2 = z.re * z.re + z.im * z.im;
+                for (size_t k = 0; k < q.size(); ++k) {
+                    nq[k + 2] = nq[k + 2] + q[k];
+                    nq[k + 1] = nq[k + 1] - q[k] * t;
+                    nq[k] = nq[k] + q[k] * s2;
+                }
+            }
+            q.swap(nq);
+        }
+        std::vector<int64_t> f(q.size());
+        bool ok = true;
+        for (size_t k = 0; k < q.size() && ok; ++k) ok = round_dd(q[k], f[k]);
+        if (!ok) continue;
+        make_primitive(f);
+        if (f.back() <= 0) continue;
+        std::vector<int64_t> g;
+        bool ovf = false;
+        if (!exact_div(P.prim, f, g, ovf)) {
+            if (ovf) {
+                err = "trial division overflowed int128";
+                return RFR_EOVERFLOW;
+            }
+            continue;
+        }
+        if (g.back() <= 0) continue;
+        ++out.n_confirmed;
+        if (small_is_s) {
+            found[s0] = f;
+            found[comp] = g;
+        } else {
+            found[s0] = g;
+            found[comp] = f;
+        }
+    }
+    // atoms: the intersection of every divisor set that holds element i
+    std::vector<Pat> sets;
+    for (auto &kv : found) sets.push_back(kv.first);
+    sets.push_back(full);
+    std::vector<Pat> atoms;
+    for (int i = 0; i < n; ++i) {
+        Pat a = full;
+        for (auto &t : sets)
+            if (t.get(i)) a = a & t;
+        if (std::find(atoms.begin(), atoms.end(), a) == atoms.end()) atoms.push_back(a);
+    }
+    out.content = P.content;
+    out.factors.clear();
+    if (P.xpow == 1) out.factors.push_back({0, 1});
+    for (auto &a : atoms) {
+        if (a == full) {
+            out.factors.push_back(P.prim);
+            continue;
+        }
+        auto it = found.find(a);
+        if (it == found.end()) {
+            err = "an atom of the divisors found has no confirmed factor";
+            return RFR_EPRECISION;
+        }
+        out.factors.push_back(it->second);
+    }
+    std::sort(out.factors.begin(), out.factors.end(), canon_less);
+    return RFR_OK;
+}
+
+}  // namespace rfr

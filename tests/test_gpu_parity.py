@@ -1,0 +1,189 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bit-exact everywhere: sorted subset sums (EXPAND), candidate pattern sets on
+identical (w, t_lo, t_hi), and final factorisations (which are unique).
+"""
+import json
+import os
+import random
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import rfr_ref as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+MASK = (1 << 64) - 1
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2410_15880_amd as R
+    R.lib()
+    return R
+
+
+@pytest.fixture(scope="module")
+def ctx(R):
+    c = R.Context(0)
+    yield c
+    c.close()
+
+
+def planted_weights(rng, n, k_rel=2):
+    """Random 64-bit weights with a few exact relations planted (so the window is hit)."""
+    w = [rng.getrandbits(64) for _ in range(n)]
+    for _ in range(k_rel):
+        if n < 4:
+            break
+        idx = rng.sample(range(n - 1), min(n - 1, rng.randint(2, 6)))
+        tot = sum(w[i] for i in idx[:-1])
+        w[idx[-1]] = (-tot - rng.randint(0, n)) & MASK
+    return w
+
+
+# ------------------------------------------------------------------ EXPAND
+
+
+@pytest.mark.parametrize("m", [1, 3, 7, 8, 9, 12, 15, 19, 22])
+@pytest.mark.parametrize("negate", [False, True])
+def test_expand_matches_sorted_subset_sums(R, m, negate):
+    rng = random.Random(100 + m)
+    w = [rng.getrandbits(64) for _ in range(m)]
+    say("expand m=%d negate=%d" % (m, negate))
+    got = R.expand_dev(w, negate=negate)
+    want = O.expand(w, negate=negate)
+    assert got.shape == want.shape
+    assert np.array_equal(got, want)
+
+
+def test_expand_duplicate_heavy(R):
+    # many equal keys (zero and repeated weights) stay within one sub-bucket
+    w = [0, 0, 5, 5, 1 << 63, 7, (1 << 64) - 7, 3, 3, 3, 11]
+    say("expand duplicates")
+    assert np.array_equal(R.expand_dev(w), O.expand(w))
+
+
+# ------------------------------------------------------------------ search
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 6, 9, 12, 17, 18, 23, 26])
+def test_search_matches_bruteforce(R, n):
+    rng = random.Random(n)
+    w = planted_weights(rng, n)
+    for t_lo, t_hi in [(0, 0), (n + 5, 3), (1 << 20, 1 << 18)]:
+        say("search n=%d window=(%d,%d)" % (n, t_lo, t_hi))
+        got = R.recombine_dev(w, t_lo, t_hi, cap=1 << 16)
+        want = O.search_brute(w, t_lo, t_hi)
+        assert got == want
+
+
+@pytest.mark.parametrize("n", [30, 33, 38])
+def test_search_matches_hs_oracle(R, n):
+    rng = random.Random(1000 + n)
+    w = planted_weights(rng, n, k_rel=4)
+    t_lo, t_hi = n + 7, 5
+    say("search-hs n=%d" % n)
+    got = R.recombine_dev(w, t_lo, t_hi, cap=1 << 12)
+    want = O.search_hs(w, t_lo, t_hi)
+    assert got == want
+
+
+def test_search_closed_forms(R):
+    n = 12
+    say("closed form: zero weights")
+    assert R.recombine_dev([0] * n, 0, 0, cap=4096) == list(range(1, 1 << (n - 1)))
+    rng = random.Random(5)
+    w = [rng.getrandbits(64) for _ in range(n)]
+    w[1] = (-w[0]) & MASK
+    say("closed form: w0 = -w1")
+    assert R.recombine_dev(w, 0, 0) == [0b11]
+    say("closed form: powers of two")
+    assert R.recombine_dev([1 << i for i in range(n)], 0, 0) == []
+
+
+def test_search_window_wraps_and_edges(R):
+    # keys straddling 0 / 2^64 and sub-bucket edges
+    for n in (10, 25, 31):
+        rng = random.Random(77 + n)
+        w = [rng.getrandbits(64) for _ in range(n)]
+        w[0] = (MASK - 2)           # pattern {0} sums to -3
+        w[2] = 4                    # pattern {2} sums to +4
+        w[3] = (1 << 63) - 1
+        w[4] = (1 << 63) + 3        # {3,4} sums to +2
+        say("wrap n=%d" % n)
+        for t_lo, t_hi in [(3, 4), (2, 3), (100, 100)]:
+            assert R.recombine_dev(w, t_lo, t_hi, cap=1 << 12) == O.search_hs(w, t_lo, t_hi)
+
+
+def test_search_capacity_overflow_reported(R):
+    say("overflow")
+    with pytest.raises(R.RFRError) as e:
+        R.recombine_dev([0] * 14, 0, 0, cap=100)
+    assert e.value.name == "RFR_ECANDIDATES"
+
+
+# ------------------------------------------------------------------ end to end
+
+
+def test_textbook_and_errors(R, ctx):
+    cases = [[6, -5, 1], [-1, 0, 0, 0, 0, 0, 1], [0, -1, 0, 1], [0, 6, 6, -36], [1, 0, -10, 0, 1],
+             [-2, 0, 1], [-1, 0, 2], [3, 7], [5, 3, 7]]
+    for c in cases:
+        say("factor", c)
+        assert ctx.factor(c) == O.factor(c)
+    p = [1]
+    for k in range(1, 9):
+        p = O.poly_mul_exact(p, [-k, 1])
+    assert ctx.factor(p) == O.factor(p)
+    for bad, name in [([1, -2, 1], "RFR_ENOTSQFREE"), ([0, 0, 1], "RFR_ENOTSQFREE"), ([5], "RFR_EINVAL")]:
+        with pytest.raises(R.RFRError) as e:
+            ctx.factor(bad)
+        assert e.value.name == name
+
+
+def test_config_small_exact(ctx):
+    w = W.config_small()
+    say("config small")
+    assert ctx.factor(w.coeffs) == O.factor(w.coeffs)
+
+
+def test_config_mid_exact_vs_golden(ctx):
+    g = json.load(open(os.path.join(HERE, "golden", "golden_mid.json")))["cases"]
+    for w in W.config_mid():
+        say("config mid seed", w.seed)
+        e = g[str(w.seed)]
+        assert w.coeffs == e["coeffs"]
+        assert ctx.factor(w.coeffs) == (e["content"], [tuple(f) for f in e["factors"]])
+
+
+def test_config_large_exact_vs_golden(ctx):
+    g = json.load(open(os.path.join(HERE, "golden", "golden_large.json")))["cases"]
+    for w in W.config_large():
+        say("config large seed", w.seed)
+        e = g[str(w.seed)]
+        r = ctx.factor_full(w.coeffs)
+        assert (r["content"], r["factors"]) == (e["content"], [tuple(f) for f in e["factors"]])
+        say("  n=%d candidates=%d confirmed=%d window=(%d,%d) ms roots/search/confirm %.1f/%.1f/%.1f" % (
+            r["n"], r["n_candidates"], r["n_confirmed"], r["t_lo"], r["t_hi"], r["ms_roots"],
+            r["ms_search"], r["ms_confirm"]))
+
+
+def test_repeat_runs_identical(R):
+    # identical candidate sets across repeated launches (race check)
+    rng = random.Random(9)
+    w = planted_weights(rng, 34, k_rel=6)
+    say("repeat n=34")
+    first = R.recombine_dev(w, 40, 6)
+    for _ in range(3):
+        assert R.recombine_dev(w, 40, 6) == first
