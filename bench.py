@@ -1,0 +1,167 @@
+"""Benchmark of the RFR hot path on one MI355X.
+
+One step = the whole path (roots, weights, window, device search, confirmation,
+atoms) over one batch of 16 seeded degree-100 polynomials (8 random with
+coefficients in [-1000, 1000], 8 planted products of degree-30 and degree-70
+factors), through the library's batched entry point.
+
+Prints ONE JSON line.  `value` is subset-sum pairs per second: sum over the
+batch of N_A * N_B = 2^(n-1) (the pattern space each search covers) divided by
+the step time.  The roofline object reports the dominant search kernel's
+algorithmic bytes per launch over its average launch duration, timed with HIP
+events recorded on the stream the kernel runs on, inside the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic HBM bytes per table key for each stage:
+# K1 writes each key once; K2 reads and writes it; K3 reads it; K0/K4 only
+# enumerate (no table traffic); the scans touch per-workgroup counters only.
+STAGE_BYTES_PER_KEY = {"count": 0, "scan": 0, "enum_partition": 8, "tile_sort": 16, "sort_join": 8,
+                       "recover": 0}
+STAGE_KERNEL = {"count": "k_enum<true>", "scan": "k_scan_cols+k_scan_buckets",
+                "enum_partition": "k_enum<false>", "tile_sort": "k_tile2", "sort_join": "k_join<false>",
+                "recover": "k_recover+k_pairs"}
+
+
+def host_info():
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def cpu_baseline(polys, ns):
+    """The oracle, as it stands, on one polynomial of the workload (bounded sample)."""
+    from oracle import rfr_ref as O
+    i = 0
+    t0 = time.perf_counter()
+    got = O.factor(polys[i].coeffs)
+    dt = time.perf_counter() - t0
+    pairs = 2 ** (ns[i] - 1)
+    return {"value": pairs / dt, "unit": "pairs/s", "cores": 1, "kind": "oracle",
+            "seconds": round(dt, 2),
+            "factorizations_per_s": 1.0 / dt,
+            "sample": "1 of the 16 degree-100 polynomials (seed %d, %s, n=%d): oracle.factor end to end, "
+                      "single thread (numpy sort/searchsorted, mpmath roots)" % (
+                          polys[i].seed, polys[i].kind, ns[i])}, got
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(independent polynomials would shard with no communication; see DESIGN.md).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2410_15880_amd as R
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    polys = W.config_large()
+    coeffs = [w.coeffs for w in polys]
+    ns = [R.weights(c)["n"] for c in coeffs]
+    pairs_per_step = sum(2 ** (n - 1) for n in ns)
+    keys_per_step = 0
+    for n in ns:
+        n1 = n - 1
+        keys_per_step += 2 ** ((n1 + 1) // 2) + 2 ** (n1 // 2)
+
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "golden_large.json")))["cases"]
+    ctx = R.Context(0)
+    for _ in range(args.warmup):
+        res = ctx.factor_batch(coeffs)
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = ctx.factor_batch(coeffs)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ctx.close()
+
+    ok = all(not isinstance(r, Exception) and r == (golden[str(w.seed)]["content"],
+                                                     [tuple(f) for f in golden[str(w.seed)]["factors"]])
+             for r, w in zip(res, polys))
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+    value = pairs_per_step / (ms_per_step / 1000.0)
+
+    nsearch = max(prof["searches"], 1)
+    stage_avg = {k: v / nsearch for k, v in prof["stage_ms"].items()}
+    dom = max(stage_avg, key=lambda k: stage_avg[k])
+    keys_per_launch = prof["keys"] / nsearch
+    alg_bytes = STAGE_BYTES_PER_KEY[dom] * keys_per_launch
+    achieved = alg_bytes / (stage_avg[dom] / 1000.0) / 1e9 if stage_avg[dom] > 0 else 0.0
+    if STAGE_BYTES_PER_KEY[dom] > 0:
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": STAGE_KERNEL[dom], "avg_launch_ms": round(stage_avg[dom], 4),
+                    "alg_bytes_per_launch": int(alg_bytes)}
+    else:
+        roofline = {"bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None,
+                    "traffic": None, "kernel": STAGE_KERNEL[dom], "avg_launch_ms": round(stage_avg[dom], 4)}
+    stage_gbs = {}
+    for k, v in stage_avg.items():
+        b = STAGE_BYTES_PER_KEY[k] * keys_per_launch
+        stage_gbs[k] = round(b / (v / 1000.0) / 1e9, 1) if (b > 0 and v > 0) else None
+
+    out = {
+        "metric": "subset-sum pairs/s + degree-100 factorizations/s; p50/p99 latency vs plain",
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "degree-100 x16: 8 random in [-1000,1000] + 8 planted 30x70 products "
+                               "(seeds 3000-3015), plain RFR per polynomial",
+                   "polys": len(polys), "degree": 100, "n_elements": ns,
+                   "pairs_per_step": pairs_per_step, "keys_per_step": keys_per_step},
+        "factorizations_per_s": len(polys) / (ms_per_step / 1000.0),
+        "results_match_oracle": ok,
+        "stage_ms_per_search": {k: round(v, 4) for k, v in stage_avg.items()},
+        "stage_alg_gbs": stage_gbs,
+        "roofline": roofline,
+        "host": host_info(),
+    }
+    if not args.no_cpu_baseline:
+        cb, got = cpu_baseline(polys, ns)
+        out["cpu_baseline"] = cb
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

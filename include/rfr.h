@@ -134,6 +134,23 @@ rfr_status rfr_poll(rfr_ctx *ctx, uint64_t ticket, rfr_result **out, double *lat
 /* Stop the serving loop after draining queued requests. */
 rfr_status rfr_serve_stop(rfr_ctx *ctx);
 
+/* ------------------------------------------------------------------ profiling */
+
+/* Device time per search stage, accumulated from HIP events recorded on the
+ * stream each stage runs on, while profiling is enabled on the context.
+ * stage_ms: [0] K0 count, [1] scans, [2] K1 enumerate+partition,
+ * [3] K2 tile sort, [4] K3 sort+join, [5] K4+K5 pattern recovery.
+ * keys: sum of N_A + N_B over the profiled searches. */
+typedef struct rfr_profile_t {
+    uint64_t searches;
+    uint64_t keys;
+    double stage_ms[6];
+} rfr_profile_t;
+
+/* enable != 0 starts (and zeroes) accumulation, 0 stops it. */
+rfr_status rfr_profile(rfr_ctx *ctx, int enable);
+rfr_status rfr_profile_read(rfr_ctx *ctx, rfr_profile_t *out);
+
 /* ------------------------------------------------------------------ results */
 
 void rfr_result_free(rfr_result *res);

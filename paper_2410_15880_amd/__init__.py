@@ -27,6 +27,7 @@ EXPORTS = [
     "rfr_serve_start", "rfr_submit", "rfr_poll", "rfr_serve_stop", "rfr_result_free",
     "rfr_strerror", "rfr_last_error", "rfr_weights", "rfr_recombine_workspace_bytes",
     "rfr_recombine_dev", "rfr_expand_workspace_bytes", "rfr_expand_dev",
+    "rfr_profile", "rfr_profile_read",
 ]
 
 
@@ -35,6 +36,13 @@ class RFRError(RuntimeError):
         super().__init__("%s: %s" % (STATUS.get(status, status), msg))
         self.status = status
         self.name = STATUS.get(status, str(status))
+
+
+class Profile(C.Structure):
+    _fields_ = [("searches", C.c_uint64), ("keys", C.c_uint64), ("stage_ms", C.c_double * 6)]
+
+
+STAGES = ["count", "scan", "enum_partition", "tile_sort", "sort_join", "recover"]
 
 
 class Result(C.Structure):
@@ -81,6 +89,8 @@ def lib():
         "rfr_recombine_dev": ([C.POINTER(u64), C.c_int, u64, u64, P, sz, P, P, u64, P], C.c_int),
         "rfr_expand_workspace_bytes": ([C.c_int], sz),
         "rfr_expand_dev": ([C.POINTER(u64), C.c_int, C.c_int, P, sz, P, P], C.c_int),
+        "rfr_profile": ([P, C.c_int], C.c_int),
+        "rfr_profile_read": ([P, C.POINTER(Profile)], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -177,6 +187,16 @@ class Context:
             else:
                 res.append(RFRError(sts[i], "batch entry %d" % i))
         return res
+
+    # ---- profiling
+    def profile(self, enable: bool = True):
+        _check(lib().rfr_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        pr = Profile()
+        _check(lib().rfr_profile_read(self._h, C.byref(pr)))
+        return {"searches": int(pr.searches), "keys": int(pr.keys),
+                "stage_ms": {k: float(pr.stage_ms[i]) for i, k in enumerate(STAGES)}}
 
     # ---- serving
     def serve_start(self, max_active: int = 8, host_threads: int = 16):

@@ -102,13 +102,15 @@ rfr_status search_on_slot(rfr_ctx *ctx, Slot &s, const Prepared &P, std::vector<
     rfr_status st = ensure_workspace(ctx, s, need);
     if (st != RFR_OK) return st;
     std::string err;
+    const bool prof = ctx->profiling && !ctx->serving;
     st = enqueue_recombine(P.w.data(), P.n, P.t_lo, P.t_hi, s.ws, s.ws_bytes, s.stream, s.cand_dev, s.cap,
-                           s.count_dev, nullptr, err);
+                           s.count_dev, prof ? profile_events(ctx, 0) : nullptr, err);
     if (st != RFR_OK) return fail(st, err);
     uint64_t *hcount = s.host + 2 * s.cap;
     if (hipMemcpyAsync(hcount, s.count_dev, 8, hipMemcpyDeviceToHost, s.stream) != hipSuccess ||
         hipStreamSynchronize(s.stream) != hipSuccess)
         return fail(RFR_EDEVICE, "device search failed");
+    if (prof) profile_collect(ctx, 0, P.n);
     uint64_t cnt = *hcount;
     if (cnt == ~0ull) return fail(RFR_ECANDIDATES, "candidate capacity exceeded");
     if (cnt) {
@@ -199,6 +201,8 @@ void rfr_destroy(rfr_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     rfr_serve_stop(ctx);
     batch_release(ctx);
+    for (auto e : ctx->prof_ev)
+        if (e) (void)hipEventDestroy(e);
     slot_free(ctx, ctx->main);
     delete ctx;
 }

@@ -61,6 +61,11 @@ struct rfr_ctx {
     bool stopping = false;
     // ---- batch
     rfr::BatchState *batch = nullptr;
+    // ---- profiling (per-stage HIP events)
+    bool profiling = false;
+    rfr_profile_t prof{};
+    std::vector<hipEvent_t> prof_ev;
+    std::vector<rfr::StageEvents> prof_se;
 };
 
 namespace rfr {
@@ -74,4 +79,6 @@ void slot_free(rfr_ctx *ctx, Slot &s);
 rfr_status search_on_slot(rfr_ctx *ctx, Slot &s, const Prepared &P, std::vector<Pat> &cands);
 rfr_status factor_on_slot(rfr_ctx *ctx, Slot &s, const int64_t *coeffs, int degree, rfr_result **out);
 void batch_release(rfr_ctx *ctx);
+StageEvents *profile_events(rfr_ctx *ctx, int k);
+void profile_collect(rfr_ctx *ctx, int k, int n);
 }  // namespace rfr
