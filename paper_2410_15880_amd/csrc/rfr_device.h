@@ -22,15 +22,16 @@ constexpr int MAXB1_LOG = 10;     // level-1 digit bits (buckets) at most
 constexpr int MAXB1 = 1 << MAXB1_LOG;
 // ---- K2: per-bucket tile sort by the level-2 digit
 constexpr int NT2 = 512;
-constexpr int T2 = 8192;          // keys per tile (<= 65535: u16 digit offsets)
+constexpr int T2 = 4096;          // keys per tile (<= 65535: u16 digit offsets)
 constexpr int KPT2 = T2 / NT2;
 constexpr int MAXB2_LOG = 10;
 constexpr int MAXB2 = 1 << MAXB2_LOG;
-// ---- K3: sub-bucket gather, LDS sort, merge-path band join
+// ---- K3: sub-bucket gather, LDS radix sort of B', band join probing it with A
 constexpr int NT3 = 256;
-constexpr int CAP3 = 2048;        // keys per half held in LDS (mean is ~1024)
-constexpr int KPT3 = CAP3 / NT3;
-constexpr int LB3 = 10;           // bits of the in-LDS counting sort
+constexpr int SUB_LOG = 11;       // mean keys of the larger half per sub-bucket = 2^SUB_LOG
+constexpr int KP3 = 12;           // key slots per thread per half (registers)
+constexpr int CAP3 = NT3 * KP3;   // keys per half a sub-bucket may hold on the fast path
+constexpr int LB3 = 10;           // bits of the in-LDS counting sort of B'
 constexpr int NB3 = 1 << LB3;
 constexpr int MAXT = 256;         // tile rows staged per gather chunk
 // ---- K4/K5: candidate keys -> patterns
@@ -38,6 +39,8 @@ constexpr int KCAP_MAX = 4096;    // key pairs held per search
 constexpr int RBITS_LOG = 16;     // LDS bitmap of candidate-key prefixes
 constexpr int RBITS = 1 << RBITS_LOG;
 constexpr int MAX_HALF = 34;      // elements per half (2^34 keys)
+constexpr int RECOVER_FEW = 64;   // candidate keys handled by the meet-in-the-middle recovery
+constexpr int SPT4 = 16;          // Gray steps per thread in that recovery
 
 struct HalfArgs {
     uint64_t *keys;      // [N] partitioned keys

@@ -127,7 +127,7 @@ __global__ void k_init(JobArgs J) {
 // low L pattern bits (its partial sum is fixed); step h selects the high bits
 // gray(h) = h ^ (h >> 1), so going from h to h+1 flips exactly bit ctz(h+1) and
 // changes the high sum by one wavefront-uniform +-w.
-template <bool COUNT>
+template <bool COUNT, int NBMAX>
 __global__ __launch_bounds__(NT1) void k_enum(JobArgs J) {
     const HalfArgs &H = J.h[blockIdx.y];
     const uint32_t wg = blockIdx.x;
@@ -141,9 +141,9 @@ __global__ __launch_bounds__(NT1) void k_enum(JobArgs J) {
     const bool act = tid < nl;
 
     __shared__ uint64_t s_w[64];
-    __shared__ uint32_t s_cnt[MAXB1];
-    __shared__ uint32_t s_off[MAXB1];
-    __shared__ uint64_t s_cur[MAXB1];
+    __shared__ uint32_t s_cnt[NBMAX];
+    __shared__ uint32_t s_off[NBMAX];
+    __shared__ uint64_t s_cur[COUNT ? 1 : NBMAX];
     __shared__ uint64_t s_tmp[NT1 / 64 + 1];
     __shared__ uint64_t s_buf[COUNT ? 1 : T1];
 
@@ -189,9 +189,17 @@ __global__ __launch_bounds__(NT1) void k_enum(JobArgs J) {
         for (int k = 0; k < KPT1; ++k)
             if (act && k < ns) rank[k] = atomicAdd(&s_cnt[dig(key[k], sh1, m1)], 1u);
         __syncthreads();
-        for (int b = tid; b < nb; b += NT1) s_off[b] = s_cnt[b];
-        __syncthreads();
-        lds_excl_scan<NT1, MAXB1 / NT1>(s_off, nb, s_tmp);
+        if (NBMAX == NT1) {
+            uint64_t tot;
+            const uint32_t c = tid < nb ? s_cnt[tid] : 0;
+            const uint64_t ex = block_excl_scan<NT1>(c, s_tmp, &tot);
+            if (tid < nb) s_off[tid] = (uint32_t)ex;
+            __syncthreads();
+        } else {
+            for (int b = tid; b < nb; b += NT1) s_off[b] = s_cnt[b];
+            __syncthreads();
+            lds_excl_scan<NT1, NBMAX / NT1>(s_off, nb, s_tmp);
+        }
 #pragma unroll
         for (int k = 0; k < KPT1; ++k)
             if (act && k < ns) {
@@ -268,6 +276,7 @@ __global__ __launch_bounds__(NT1) void k_scan_buckets(JobArgs J) {
 // One tile (<= T2 keys) of one level-1 bucket: counting sort by the level-2
 // digit in LDS, written back in place; digstart[d][tile] = offset of digit d
 // inside the tile, digstart[nd][tile] = tile length.
+template <int NBMAX>
 __global__ __launch_bounds__(NT2) void k_tile2(JobArgs J) {
     const HalfArgs &H = J.h[blockIdx.y];
     const int nb = 1 << J.B1;
@@ -280,8 +289,8 @@ __global__ __launch_bounds__(NT2) void k_tile2(JobArgs J) {
     const int tid = threadIdx.x;
 
     __shared__ uint64_t s_buf[T2];
-    __shared__ uint32_t s_cnt[MAXB2];
-    __shared__ uint32_t s_off[MAXB2];
+    __shared__ uint32_t s_cnt[NBMAX];
+    __shared__ uint32_t s_off[NBMAX];
     __shared__ uint64_t s_tmp[NT2 / 64 + 1];
     __shared__ int s_b;
 
@@ -302,18 +311,21 @@ __global__ __launch_bounds__(NT2) void k_tile2(JobArgs J) {
 
     uint64_t key[KPT2];
     uint32_t rank[KPT2];
+    // all loads first (independent, in flight together), then the ranks
 #pragma unroll
     for (int k = 0; k < KPT2; ++k) {
         const int p = tid + k * NT2;
-        if (p < len) {
-            key[k] = H.keys[base + p];
-            rank[k] = atomicAdd(&s_cnt[dig(key[k], sh2, m2)], 1u);
-        }
+        if (p < len) key[k] = __builtin_nontemporal_load(&H.keys[base + p]);
+    }
+#pragma unroll
+    for (int k = 0; k < KPT2; ++k) {
+        const int p = tid + k * NT2;
+        if (p < len) rank[k] = atomicAdd(&s_cnt[dig(key[k], sh2, m2)], 1u);
     }
     __syncthreads();
     for (int d = tid; d < nd; d += NT2) s_off[d] = s_cnt[d];
     __syncthreads();
-    lds_excl_scan<NT2, MAXB2 / NT2>(s_off, nd, s_tmp);
+    lds_excl_scan<NT2, (NBMAX + NT2 - 1) / NT2>(s_off, nd, s_tmp);
 #pragma unroll
     for (int k = 0; k < KPT2; ++k) {
         const int p = tid + k * NT2;
@@ -353,92 +365,6 @@ __device__ __forceinline__ void for_each_global(const HalfArgs &H, int B2, int b
     }
 }
 
-// Gather sub-bucket (b, d) of half H into s_keys; returns its size (may
-// exceed CAP3, in which case nothing beyond CAP3 is stored).
-__device__ uint32_t gather_sub(const HalfArgs &H, int B2, int b, int d, uint64_t *s_keys,
-                               uint32_t *s_st, uint32_t *s_len, uint64_t *s_tmp) {
-    const SubRef r = sub_ref(H, b);
-    const uint32_t nt = r.t1 - r.t0;
-    uint32_t total = 0;
-    // tile rows in chunks of MAXT tiles
-    for (uint32_t c0 = 0; c0 < nt; c0 += MAXT) {
-        const uint32_t cn = min((uint32_t)MAXT, nt - c0);
-        for (uint32_t i = threadIdx.x; i < cn; i += NT3) {
-            const uint32_t t = r.t0 + c0 + i;
-            const uint32_t s = H.digstart[(size_t)d * H.ntile2_max + t];
-            const uint32_t e = H.digstart[(size_t)(d + 1) * H.ntile2_max + t];
-            s_st[i] = s;
-            s_len[i] = e - s;
-        }
-        __syncthreads();
-        // prefix of lengths (serial per wave is enough: cn <= MAXT)
-        if (threadIdx.x == 0) {
-            uint32_t acc = total;
-            for (uint32_t i = 0; i < cn; ++i) {
-                const uint32_t l = s_len[i];
-                s_len[i] = acc;  // becomes the LDS destination offset
-                acc += l;
-            }
-            s_tmp[0] = acc;
-        }
-        __syncthreads();
-        const uint32_t acc = (uint32_t)s_tmp[0];
-        // one wavefront per tile segment
-        const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-        for (uint32_t i = wv; i < cn; i += NT3 / 64) {
-            const uint32_t dst = s_len[i];
-            const uint32_t end = (i + 1 < cn) ? s_len[i + 1] : acc;
-            const uint32_t len = end - dst;
-            const uint64_t src = r.pos0 + (uint64_t)(c0 + i) * T2 + s_st[i];
-            for (uint32_t q = lane; q < len; q += 64)
-                if (dst + q < CAP3) s_keys[dst + q] = H.keys[src + q];
-        }
-        total = acc;
-        __syncthreads();
-    }
-    return total;
-}
-
-// Counting sort of s_keys[0..cnt) by the B3-bit digit at shift sh3, in place
-// (keys staged in registers), then insertion sort inside each digit bin: the
-// result is fully sorted.  s_bin must hold NB3 + 1 entries.
-__device__ void lds_sort(uint64_t *s_keys, uint32_t cnt, int sh3, uint32_t *s_bin, uint64_t *s_tmp) {
-    for (int i = threadIdx.x; i < NB3; i += NT3) s_bin[i] = 0;
-    __syncthreads();
-    uint64_t key[KPT3];
-    uint32_t rank[KPT3];
-#pragma unroll
-    for (int k = 0; k < KPT3; ++k) {
-        const uint32_t p = threadIdx.x + k * NT3;
-        if (p < cnt) {
-            key[k] = s_keys[p];
-            rank[k] = atomicAdd(&s_bin[dig(key[k], sh3, NB3 - 1)], 1u);
-        }
-    }
-    __syncthreads();
-    lds_excl_scan<NT3, NB3 / NT3>(s_bin, NB3, s_tmp);
-    if (threadIdx.x == 0) s_bin[NB3] = cnt;
-#pragma unroll
-    for (int k = 0; k < KPT3; ++k) {
-        const uint32_t p = threadIdx.x + k * NT3;
-        if (p < cnt) s_keys[s_bin[dig(key[k], sh3, NB3 - 1)] + rank[k]] = key[k];
-    }
-    __syncthreads();
-    for (int bn = threadIdx.x; bn < NB3; bn += NT3) {
-        const uint32_t s = s_bin[bn], e = s_bin[bn + 1];
-        for (uint32_t i = s + 1; i < e; ++i) {
-            const uint64_t v = s_keys[i];
-            uint32_t j = i;
-            while (j > s && s_keys[j - 1] > v) {
-                s_keys[j] = s_keys[j - 1];
-                --j;
-            }
-            s_keys[j] = v;
-        }
-    }
-    __syncthreads();
-}
-
 // Partners of a in a neighbouring sub-bucket `ns` of half B' (slow path, rare):
 // every key b there with b' - a in the window, except those the in-bucket
 // merge already reported (b in [lo, hi] and inside sub-bucket s).
@@ -453,128 +379,322 @@ __device__ void edge_scan(const JobArgs &J, uint64_t a, uint32_t s, uint32_t ns,
     });
 }
 
+// Gather sub-bucket (b, d) of NH halves into register slots: key q of half h
+// (q = tid + k*NT3) lands in kk[h][k].  The bucket's tiles are taken in chunks
+// of MAXT: each thread reads one tile's digit-d segment bounds per half, one
+// packed block scan (half 0 low 32 bits, half 1 high) gives the segments' key
+// offsets, an LDS tile map q -> tile lets every thread address its keys
+// directly, and all slot loads of a chunk are in flight together.  Returns
+// the key counts; counts beyond CAP3 are reported but not loaded.
+template <int NH>
+__device__ __forceinline__ void gather_regs(const JobArgs &J, int b, int d, uint64_t (&kk)[2][KP3],
+                                            uint32_t (&n)[2], uint32_t (*s_st)[MAXT], uint32_t (*s_off)[MAXT + 1],
+                                            uint8_t (*s_tmap)[CAP3], uint64_t *s_tmp) {
+    const int tid = threadIdx.x;
+    SubRef r[2];
+    uint32_t nt[2] = {0, 0};
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+        r[h] = sub_ref(J.h[h], b);
+        nt[h] = r[h].t1 - r[h].t0;
+    }
+    const uint32_t ntmax = max(nt[0], NH > 1 ? nt[1] : 0u);
+    uint32_t base[2] = {0, 0};
+    for (uint32_t c0 = 0; c0 < ntmax; c0 += MAXT) {
+        unsigned long long mine = 0;
+        uint32_t len[2] = {0, 0};
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+            const HalfArgs &H = J.h[h];
+            const uint32_t t = c0 + tid;
+            if (t < nt[h]) {
+                const uint32_t st = H.digstart[(size_t)d * H.ntile2_max + r[h].t0 + t];
+                const uint32_t en = H.digstart[(size_t)(d + 1) * H.ntile2_max + r[h].t0 + t];
+                s_st[h][tid] = st;
+                len[h] = en - st;
+            }
+        }
+        mine = (unsigned long long)len[0] | ((unsigned long long)len[1] << 32);
+        uint64_t tot;
+        const unsigned long long pre = block_excl_scan<NT3>(mine, s_tmp, &tot);
+        const uint32_t cl[2] = {(uint32_t)tot, (uint32_t)(tot >> 32)};
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+            s_off[h][tid] = h ? (uint32_t)(pre >> 32) : (uint32_t)pre;
+            if (tid == 0) s_off[h][MAXT] = cl[h];
+        }
+        __syncthreads();
+        const int wv = tid >> 6, lane = tid & 63;
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+            const uint32_t cn = nt[h] > c0 ? min((uint32_t)MAXT, nt[h] - c0) : 0u;
+            for (uint32_t t = wv; t < cn; t += NT3 / 64) {
+                const uint32_t o = s_off[h][t], e = (t + 1 < cn) ? s_off[h][t + 1] : cl[h];
+                for (uint32_t q = o + lane; q < e; q += 64)
+                    if (base[h] + q < CAP3) s_tmap[h][base[h] + q] = (uint8_t)t;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+            const HalfArgs &H = J.h[h];
+#pragma unroll
+            for (int k = 0; k < KP3; ++k) {
+                const uint32_t q = tid + k * NT3;
+                if (q >= base[h] && q < base[h] + cl[h] && q < CAP3) {
+                    const uint32_t t = s_tmap[h][q];
+                    kk[h][k] = __builtin_nontemporal_load(
+                        &H.keys[r[h].pos0 + (uint64_t)(c0 + t) * T2 + s_st[h][t] + (q - base[h] - s_off[h][t])]);
+                }
+            }
+            base[h] += cl[h];
+        }
+        __syncthreads();
+    }
+    n[0] = base[0];
+    n[1] = base[1];
+}
+
+// Counting sort of the keys in kk[0..n) (register slots) into s_out by the
+// LB3-bit digit at shift sh3; s_bin[0..NB3] receives the bin starts (and n).
+// With `full`, each bin is then insertion-sorted, so s_out is fully sorted.
+__device__ __forceinline__ void sort_slots(const uint64_t (&kk)[KP3], uint32_t n, int sh3, uint64_t *s_out,
+                                           uint32_t *s_bin, uint64_t *s_tmp, bool full) {
+    uint32_t rk[KP3];
+#pragma unroll
+    for (int k = 0; k < KP3; ++k) {
+        const uint32_t q = threadIdx.x + k * NT3;
+        if (q < n) rk[k] = atomicAdd(&s_bin[dig(kk[k], sh3, NB3 - 1)], 1u);
+    }
+    __syncthreads();
+    lds_excl_scan<NT3, NB3 / NT3>(s_bin, NB3, s_tmp);
+    if (threadIdx.x == 0) s_bin[NB3] = n;
+#pragma unroll
+    for (int k = 0; k < KP3; ++k) {
+        const uint32_t q = threadIdx.x + k * NT3;
+        if (q < n) s_out[s_bin[dig(kk[k], sh3, NB3 - 1)] + rk[k]] = kk[k];
+    }
+    __syncthreads();
+    if (!full) return;
+    for (int bn = threadIdx.x; bn < NB3; bn += NT3) {
+        const uint32_t s = s_bin[bn], e = s_bin[bn + 1];
+        for (uint32_t i = s + 1; i < e; ++i) {
+            const uint64_t v = s_out[i];
+            uint32_t j = i;
+            while (j > s && s_out[j - 1] > v) {
+                s_out[j] = s_out[j - 1];
+                --j;
+            }
+            s_out[j] = v;
+        }
+    }
+    __syncthreads();
+}
+
+// Over-capacity fallback: every a of A's sub-bucket s against every key of the
+// distinct sub-buckets s-1, s, s+1 of B', straight from global memory.
+__device__ void join_fallback(const JobArgs &J, uint32_t s, uint32_t NS, int b, int d) {
+    if (threadIdx.x == 0) atomicOr(J.flags, 2u);
+    uint32_t nbrs[3] = {(s + NS - 1) & (NS - 1), s, (s + 1) & (NS - 1)};
+    int nn = 3;
+    if (nbrs[0] == nbrs[2]) nn = (nbrs[0] == s) ? 1 : 2;
+    if (nn == 1) nbrs[0] = s;
+    if (nn == 2) nbrs[1] = s;
+    const HalfArgs &HA = J.h[0];
+    const SubRef ra = sub_ref(HA, b);
+    for (uint32_t t = ra.t0; t < ra.t1; ++t) {
+        const uint32_t st = HA.digstart[(size_t)d * HA.ntile2_max + t];
+        const uint32_t en = HA.digstart[(size_t)(d + 1) * HA.ntile2_max + t];
+        const uint64_t tb = ra.pos0 + (uint64_t)(t - ra.t0) * T2;
+        for (uint32_t q = st + threadIdx.x; q < en; q += NT3) {
+            const uint64_t a = HA.keys[tb + q];
+            for (int k = 0; k < nn; ++k) {
+                const uint32_t ns = nbrs[k];
+                for_each_global(J.h[1], J.B2, (int)(ns >> J.B2), (int)(ns & ((1u << J.B2) - 1)), [&](uint64_t bk) {
+                    if (in_win(a, bk, J.t_lo, J.t_hi)) emit_pair(J, a, bk);
+                    return *J.kp_count <= J.kcap;
+                });
+            }
+            if (*J.kp_count > J.kcap) return;
+        }
+    }
+}
+
+// K3: one sub-bucket s = (level-1 bucket b, level-2 digit d) per workgroup;
+// consecutive sub-buckets go to the same XCD so the tile-segment cache lines
+// they share meet in one L2.
+//  1. gather both halves into register slots (gather_regs);
+//  2. LDS counting sort of B' by the LB3-bit digit below the sub-bucket prefix
+//     (one pass; with SORT_OUT the single half is fully sorted and written);
+//  3. band join: each a probes the one or two B' bins its window
+//     [a - t_hi, a + t_lo] overlaps inside the sub-bucket and emits every b'
+//     in it; a window reaching past the sub-bucket (or wrapping past 0) also
+//     scans the neighbour sub-bucket of B' from global memory (edge_scan).
 template <bool SORT_OUT>
 __global__ __launch_bounds__(NT3) void k_join(JobArgs J, uint64_t *sorted_out) {
+    constexpr int NH = SORT_OUT ? 1 : 2;
     const int LB = J.B1 + J.B2;
     const uint32_t NS = 1u << LB;
-    const uint32_t s = blockIdx.x;
+    uint32_t s = blockIdx.x;
     if (s >= NS) return;
+    if (NS >= 64) s = (s & 7) * (NS >> 3) + (s >> 3);
     const int b = (int)(s >> J.B2), d = (int)(s & ((1u << J.B2) - 1));
     const int sh3 = 64 - LB - LB3;
+    const int tid = threadIdx.x;
 
-    __shared__ uint64_t s_keys[2][CAP3];
+    __shared__ uint64_t s_b[CAP3];
     __shared__ uint32_t s_bin[NB3 + 1];
-    __shared__ uint32_t s_st[MAXT], s_len[MAXT];
+    __shared__ uint32_t s_st[2][MAXT];
+    __shared__ uint32_t s_off[2][MAXT + 1];
+    __shared__ uint8_t s_tmap[2][CAP3];
     __shared__ uint64_t s_tmp[NT3 / 64 + 2];
 
-    const uint32_t na = gather_sub(J.h[0], J.B2, b, d, s_keys[0], s_st, s_len, s_tmp);
+    for (int i = tid; i < NB3; i += NT3) s_bin[i] = 0;
+    uint64_t kk[2][KP3];
+    uint32_t n[2];
+    gather_regs<NH>(J, b, d, kk, n, s_st, s_off, s_tmap, s_tmp);
+    const uint32_t na = n[0], nb = n[1];
+
     if (SORT_OUT) {
         if (na > CAP3) {
-            if (threadIdx.x == 0) atomicOr(J.flags, 1u);
+            if (tid == 0) atomicOr(J.flags, 1u);
             return;
         }
-        lds_sort(s_keys[0], na, sh3, s_bin, s_tmp);
+        sort_slots(kk[0], na, sh3, s_b, s_bin, s_tmp, true);
         // output position: bucket start + keys of lower digits in every tile
         const SubRef r = sub_ref(J.h[0], b);
         uint64_t part = 0;
-        for (uint32_t t = r.t0 + threadIdx.x; t < r.t1; t += NT3)
+        for (uint32_t t = r.t0 + tid; t < r.t1; t += NT3)
             part += J.h[0].digstart[(size_t)d * J.h[0].ntile2_max + t];
         uint64_t tot;
         block_excl_scan<NT3>(part, s_tmp, &tot);
         const uint64_t pos = r.pos0 + tot;
-        for (uint32_t i = threadIdx.x; i < na; i += NT3) sorted_out[pos + i] = s_keys[0][i];
+        for (uint32_t i = tid; i < na; i += NT3) sorted_out[pos + i] = s_b[i];
         return;
     }
-    const uint32_t nbk = gather_sub(J.h[1], J.B2, b, d, s_keys[1], s_st, s_len, s_tmp);
+    if (na > CAP3 || nb > CAP3) {
+        join_fallback(J, s, NS, b, d);
+        return;
+    }
+    sort_slots(kk[1], nb, sh3, s_b, s_bin, s_tmp, false);
+
     const uint64_t s_lo = LB == 0 ? 0 : ((uint64_t)s << (64 - LB));
     const uint64_t s_hi = LB == 0 ? ~0ull : (s_lo + ((1ull << (64 - LB)) - 1));
     const uint64_t t_lo = J.t_lo, t_hi = J.t_hi;
-
-    if (na > CAP3 || nbk > CAP3) {
-        // over-capacity fallback: every a against every key of the (distinct)
-        // sub-buckets s-1, s, s+1 of B', straight from global memory
-        if (threadIdx.x == 0) atomicOr(J.flags, 2u);
-        uint32_t nbrs[3] = {(s + NS - 1) & (NS - 1), s, (s + 1) & (NS - 1)};
-        int nn = 3;
-        if (nbrs[0] == nbrs[2]) nn = (nbrs[0] == s) ? 1 : 2;
-        if (nn == 1) nbrs[0] = s;
-        if (nn == 2) nbrs[1] = s;
-        const HalfArgs &HA = J.h[0];
-        const SubRef ra = sub_ref(HA, b);
-        uint32_t seen = 0;
-        for (uint32_t t = ra.t0; t < ra.t1; ++t) {
-            const uint32_t st = HA.digstart[(size_t)d * HA.ntile2_max + t];
-            const uint32_t en = HA.digstart[(size_t)(d + 1) * HA.ntile2_max + t];
-            const uint64_t tb = ra.pos0 + (uint64_t)(t - ra.t0) * T2;
-            for (uint32_t q = st + threadIdx.x; q < en; q += NT3) {
-                const uint64_t a = HA.keys[tb + q];
-                for (int k = 0; k < nn; ++k) {
-                    const uint32_t ns = nbrs[k];
-                    for_each_global(J.h[1], J.B2, (int)(ns >> J.B2), (int)(ns & ((1u << J.B2) - 1)),
-                                    [&](uint64_t bk) {
-                                        if (in_win(a, bk, t_lo, t_hi)) emit_pair(J, a, bk);
-                                        return *J.kp_count <= J.kcap;
-                                    });
-                }
-                if (*J.kp_count > J.kcap) return;
-            }
-            seen += en - st;
+#pragma unroll
+    for (int k = 0; k < KP3; ++k) {
+        const uint32_t q = tid + k * NT3;
+        if (q >= na) continue;
+        const uint64_t a = kk[0][k];
+        const uint64_t wlo = a >= t_hi ? a - t_hi : 0;
+        const uint64_t whi = a <= ~0ull - t_lo ? a + t_lo : ~0ull;
+        const uint64_t clo = wlo > s_lo ? wlo : s_lo;
+        const uint64_t chi = whi < s_hi ? whi : s_hi;
+        const uint32_t b0 = dig(clo, sh3, NB3 - 1), b1 = dig(chi, sh3, NB3 - 1);
+        const uint32_t e = s_bin[b1 + 1];
+        for (uint32_t i = s_bin[b0]; i < e; ++i) {
+            const uint64_t bk = s_b[i];
+            if (bk >= wlo && bk <= whi) emit_pair(J, a, bk);
         }
-        (void)seen;
-        return;
-    }
-
-    lds_sort(s_keys[0], na, sh3, s_bin, s_tmp);
-    lds_sort(s_keys[1], nbk, sh3, s_bin, s_tmp);
-    const uint64_t *A = s_keys[0];
-    const uint64_t *B = s_keys[1];
-
-    // merge path: thread t owns diagonals [t*D, (t+1)*D) of the merged order
-    // (ties: A before B), so every thread walks the same number of elements.
-    const uint32_t total = na + nbk;
-    const uint32_t D = (total + NT3 - 1) / NT3;
-    const uint32_t k0 = min(total, threadIdx.x * D);
-    const uint32_t k1 = min(total, k0 + D);
-    uint32_t lo = k0 > nbk ? k0 - nbk : 0, hi = min(k0, na);
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (A[mid] <= B[k0 - mid - 1]) lo = mid + 1;
-        else hi = mid;
-    }
-    uint32_t i = lo, j = k0 - lo;
-    for (uint32_t k = k0; k < k1; ++k) {
-        if (j >= nbk || (i < na && A[i] <= B[j])) {
-            // A[i] consumed: B[0..j) < a <= B[j..]
-            const uint64_t a = A[i];
-            const uint64_t wlo = a >= t_hi ? a - t_hi : 0;
-            const uint64_t whi = a <= ~0ull - t_lo ? a + t_lo : ~0ull;
-            for (int q = (int)j - 1; q >= 0 && B[q] >= wlo; --q) emit_pair(J, a, B[q]);
-            for (uint32_t q = j; q < nbk && B[q] <= whi; ++q) emit_pair(J, a, B[q]);
-            // window reaching past this sub-bucket (or wrapping past 0)
-            const bool low_edge = (a - s_lo) < t_hi;
-            const bool high_edge = (s_hi - a) < t_lo;
-            if (low_edge || high_edge) {
-                const uint32_t nlo = (s + NS - 1) & (NS - 1), nhi = (s + 1) & (NS - 1);
-                if (low_edge) edge_scan(J, a, s, nlo, wlo, whi);
-                if (high_edge && !(low_edge && nhi == nlo)) edge_scan(J, a, s, nhi, wlo, whi);
-            }
-            ++i;
-        } else {
-            ++j;
+        // window reaching past this sub-bucket (or wrapping past 0)
+        const bool low_edge = (a - s_lo) < t_hi;
+        const bool high_edge = (s_hi - a) < t_lo;
+        if (low_edge || high_edge) {
+            const uint32_t nlo = (s + NS - 1) & (NS - 1), nhi = (s + 1) & (NS - 1);
+            if (low_edge) edge_scan(J, a, s, nlo, wlo, whi);
+            if (high_edge && !(low_edge && nhi == nlo)) edge_scan(J, a, s, nhi, wlo, whi);
         }
     }
 }
 
 // ------------------------------------------------------------------ K4
-// Re-enumerate one half (same Gray walk as K1, no stores) and record every
-// (key, pattern) whose key occurs among the candidate key pairs.
+// Pattern recovery when few candidate keys exist (the usual case): a key of
+// this half is slo[l] + shi(g) with l the low L pattern bits and g = gray(h)
+// the high ones.  The 2^L low sums are sorted once in LDS; then every Gray step
+// h needs, per candidate key K, one binary search for K - shi(g) among them
+// (a meet in the middle inside the half) instead of 2^L enumerated keys.
+__global__ __launch_bounds__(NT1) void k_recover_few(JobArgs J) {
+    const int half = blockIdx.y;
+    const HalfArgs &H = J.h[half];
+    const uint64_t cnt = *J.kp_count;
+    if (cnt > RECOVER_FEW || cnt == 0) return;
+    const int tid = threadIdx.x;
+    const int nl = 1 << H.L;
+    const uint64_t h0 = ((uint64_t)blockIdx.x * NT1 + tid) * SPT4;
+    if ((uint64_t)blockIdx.x * NT1 * SPT4 >= H.steps) return;
+
+    __shared__ uint64_t s_w[64];
+    __shared__ uint64_t s_v[256], s_sorted[256];
+    __shared__ uint32_t s_lane[256];
+    __shared__ uint64_t s_list[RECOVER_FEW];
+    if (tid < H.m) s_w[tid] = J.wts[half][tid];
+    if (tid < cnt) s_list[tid] = J.kp[2 * tid + half];
+    __syncthreads();
+    if (tid < nl) {
+        uint64_t v = 0;
+        for (int i = 0; i < H.L; ++i)
+            if ((tid >> i) & 1) v += s_w[i];
+        s_v[tid] = v;
+    }
+    __syncthreads();
+    if (tid < nl) {
+        const uint64_t v = s_v[tid];
+        int rk = 0;
+        for (int l = 0; l < nl; ++l) {
+            const uint64_t u = s_v[l];
+            rk += (u < v) || (u == v && l < tid);
+        }
+        s_sorted[rk] = v;
+        s_lane[rk] = (uint32_t)tid;
+    }
+    __syncthreads();
+    if (h0 >= H.steps) return;
+    const uint64_t h1 = min(h0 + (uint64_t)SPT4, H.steps);
+    uint64_t g = h0 ^ (h0 >> 1);
+    uint64_t shi = 0;
+    for (int i = 0; i < H.m - H.L; ++i)
+        if ((g >> i) & 1) shi += s_w[H.L + i];
+    for (uint64_t h = h0; h < h1; ++h) {
+        for (uint32_t c = 0; c < cnt; ++c) {
+            const uint64_t key = s_list[c];
+            const uint64_t x = key - shi;
+            int lo = 0, hi = nl;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (s_sorted[mid] < x) lo = mid + 1;
+                else hi = mid;
+            }
+            bool dup = false;  // the same key listed twice: record it once
+            for (uint32_t c2 = 0; c2 < c && !dup; ++c2) dup = s_list[c2] == key;
+            for (int q = lo; !dup && q < nl && s_sorted[q] == x; ++q) {
+                const uint64_t pat = (uint64_t)s_lane[q] | (g << H.L);
+                const uint32_t r = atomicAdd(&J.rec_count[half], 1u);
+                if (r < J.kcap) {
+                    J.rec[((size_t)half * J.kcap + r) * 2] = key;
+                    J.rec[((size_t)half * J.kcap + r) * 2 + 1] = pat;
+                }
+            }
+        }
+        const uint64_t t = h + 1;
+        if (t < h1) {
+            const int bb = __builtin_ctzll(t);
+            g ^= 1ull << bb;
+            const uint64_t wb = s_w[H.L + bb];
+            shi += ((g >> bb) & 1) ? wb : (0 - wb);
+        }
+    }
+}
+
+// Pattern recovery for many candidate keys: re-enumerate the half (same Gray
+// walk as K1, no stores) and look every key up in an LDS bitmap of candidate
+// key prefixes, confirming hits against the list.
 __global__ __launch_bounds__(NT1) void k_recover(JobArgs J) {
     const int half = blockIdx.y;
     const HalfArgs &H = J.h[half];
     const uint32_t wg = blockIdx.x;
     if (wg >= H.nwg1) return;
     const uint64_t cnt = *J.kp_count;
-    if (cnt > J.kcap || cnt == 0) return;
+    if (cnt > J.kcap || cnt <= RECOVER_FEW) return;
     const int tid = threadIdx.x;
     const int nl = 1 << H.L;
     const bool act = tid < nl;
@@ -688,7 +808,7 @@ static void plan_half(int m, HalfPlan &h) {
 static void plan_bits(uint64_t nmax, int &B1, int &B2) {
     int lg = 0;
     while ((1ull << lg) < nmax) ++lg;
-    int LB = lg > 10 ? lg - 10 : 0;
+    int LB = lg > SUB_LOG ? lg - SUB_LOG : 0;
     if (LB <= 16) {
         B1 = LB < 8 ? LB : 8;
         B2 = LB - B1;
@@ -778,14 +898,17 @@ static hipError_t launch_front(JobPlan &P, JobArgs &J, hipStream_t st, StageEven
     };
     rec(0);
     hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, J);
-    hipLaunchKernelGGL(k_enum<true>, dim3(mw, nh), dim3(NT1), 0, st, J);
+    if (P.B1 <= 8) hipLaunchKernelGGL((k_enum<true, 256>), dim3(mw, nh), dim3(NT1), 0, st, J);
+    else hipLaunchKernelGGL((k_enum<true, MAXB1>), dim3(mw, nh), dim3(NT1), 0, st, J);
     rec(1);
     hipLaunchKernelGGL(k_scan_cols, dim3(1 << P.B1, nh), dim3(NT1), 0, st, J);
     hipLaunchKernelGGL(k_scan_buckets, dim3(1, nh), dim3(NT1), 0, st, J);
     rec(2);
-    hipLaunchKernelGGL(k_enum<false>, dim3(mw, nh), dim3(NT1), 0, st, J);
+    if (P.B1 <= 8) hipLaunchKernelGGL((k_enum<false, 256>), dim3(mw, nh), dim3(NT1), 0, st, J);
+    else hipLaunchKernelGGL((k_enum<false, MAXB1>), dim3(mw, nh), dim3(NT1), 0, st, J);
     rec(3);
-    hipLaunchKernelGGL(k_tile2, dim3((uint32_t)mt, nh), dim3(NT2), 0, st, J);
+    if (P.B2 <= 8) hipLaunchKernelGGL((k_tile2<256>), dim3((uint32_t)mt, nh), dim3(NT2), 0, st, J);
+    else hipLaunchKernelGGL((k_tile2<MAXB2>), dim3((uint32_t)mt, nh), dim3(NT2), 0, st, J);
     rec(4);
     return hipGetLastError();
 }
@@ -826,6 +949,9 @@ rfr_status enqueue_recombine(const uint64_t *w, int n, uint64_t t_lo, uint64_t t
     hipLaunchKernelGGL(k_join<false>, dim3(1u << (P.B1 + P.B2)), dim3(NT3), 0, st, J, (uint64_t *)nullptr);
     if (ev && ev->ev[5]) (void)hipEventRecord((hipEvent_t)ev->ev[5], st);
     uint32_t mw = std::max(P.h[0].nwg1, P.h[1].nwg1);
+    const uint64_t msteps = std::max(P.h[0].steps, P.h[1].steps);
+    const uint32_t g4 = (uint32_t)((msteps + (uint64_t)NT1 * SPT4 - 1) / ((uint64_t)NT1 * SPT4));
+    hipLaunchKernelGGL(k_recover_few, dim3(g4, 2), dim3(NT1), 0, st, J);
     hipLaunchKernelGGL(k_recover, dim3(mw, 2), dim3(NT1), 0, st, J);
     hipLaunchKernelGGL(k_pairs, dim3(1), dim3(NT1), 0, st, J);
     if (ev && ev->ev[6]) (void)hipEventRecord((hipEvent_t)ev->ev[6], st);
