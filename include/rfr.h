@@ -140,11 +140,16 @@ rfr_status rfr_serve_stop(rfr_ctx *ctx);
  * stream each stage runs on, while profiling is enabled on the context.
  * stage_ms: [0] K0 count, [1] scans, [2] K1 enumerate+partition,
  * [3] K2 tile sort, [4] K3 sort+join, [5] K4+K5 pattern recovery.
- * keys: sum of N_A + N_B over the profiled searches. */
+ * keys: sum of N_A + N_B over the profiled searches.  In a batch, one launch
+ * of each stage serves all searches of the batch, so stage_ms is per launch
+ * sequence, not per search. */
 typedef struct rfr_profile_t {
     uint64_t searches;
     uint64_t keys;
     double stage_ms[6];
+    uint64_t launches;         /* batched pipeline launches profiled (one per stage per batch) */
+    uint64_t graph_captures;   /* batch HIP graphs captured / replayed on this context */
+    uint64_t graph_replays;
 } rfr_profile_t;
 
 /* enable != 0 starts (and zeroes) accumulation, 0 stops it. */

@@ -39,7 +39,8 @@ class RFRError(RuntimeError):
 
 
 class Profile(C.Structure):
-    _fields_ = [("searches", C.c_uint64), ("keys", C.c_uint64), ("stage_ms", C.c_double * 6)]
+    _fields_ = [("searches", C.c_uint64), ("keys", C.c_uint64), ("stage_ms", C.c_double * 6),
+                ("launches", C.c_uint64), ("graph_captures", C.c_uint64), ("graph_replays", C.c_uint64)]
 
 
 STAGES = ["count", "scan", "enum_partition", "tile_sort", "sort_join", "recover"]
@@ -195,7 +196,8 @@ class Context:
     def profile_read(self) -> dict:
         pr = Profile()
         _check(lib().rfr_profile_read(self._h, C.byref(pr)))
-        return {"searches": int(pr.searches), "keys": int(pr.keys),
+        return {"searches": int(pr.searches), "keys": int(pr.keys), "launches": int(pr.launches),
+                "graph_captures": int(pr.graph_captures), "graph_replays": int(pr.graph_replays),
                 "stage_ms": {k: float(pr.stage_ms[i]) for i, k in enumerate(STAGES)}}
 
     # ---- serving

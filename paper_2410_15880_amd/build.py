@@ -37,7 +37,7 @@ UNITS = [
     ("rfr_device.hip", "hip"),
     ("rfr_host.cpp", "gxx"),
     ("rfr_abi.cpp", "hiphost"),
-    ("rfr_batch.cpp", "hiphost"),
+    ("rfr_batch.cpp", "hip"),
     ("rfr_serve.cpp", "hiphost"),
 ]
 

@@ -1,49 +1,101 @@
-// Batched factorisation: many polynomials of uneven degree in one call.
+// Batched factorisation: many polynomials of uneven degree in one device pass.
 //
-// Host roots/weights run on a thread pool (largest degree first) while the
-// device thread queues each ready polynomial's search back-to-back on one
-// stream: no host synchronisation between searches, one workspace reused in
-// stream order, and per-search candidate regions copied back with one small
-// asynchronous copy each.  After a wave of searches completes, candidates are
-// confirmed on the thread pool.
+//  1. host roots / weights / window for every polynomial on a thread pool;
+//  2. the searches are split by size: small ones (both halves <= 2^SMALL_HALF
+//     keys) go to one persistent kernel (a workgroup per polynomial, largest
+//     first from an atomic queue, everything in LDS); larger ones run through
+//     the staged pipeline with ONE launch per stage for all of them (each
+//     block finds its job from per-stage block offsets);
+//  3. the whole device pass -- descriptor upload, both paths on two streams,
+//     a summary gather and one copy back -- is captured once into a HIP graph
+//     and replayed for every later batch with the same shape;
+//  4. candidates are confirmed on the thread pool.
 #include <algorithm>
 #include <atomic>
+#include <cstring>
 #include <numeric>
+#include <sstream>
 #include <thread>
 
 #include "rfr_ctx.h"
 
 namespace rfr {
 
-constexpr int WAVE = 256;          // searches queued per synchronisation
-constexpr uint64_t BCAP = 1024;    // candidate patterns per search in a wave
-constexpr uint64_t HEAD = 64;      // candidate pairs copied back with the count
-constexpr size_t REGION = 8 + 2 * BCAP * 8;
+constexpr uint64_t BCAP = 1024;  // candidate patterns per search in a batch
+constexpr uint64_t HEAD = 8;     // pairs returned with each count
+constexpr int HUGE_HALF = 23;    // searches with a half of >= 2^23 keys are streamed one by one
+constexpr size_t SUMMARY = 1 + 2 * HEAD;  // u64 per job in the summary
 
 struct BatchState {
-    char *dev = nullptr;   // WAVE regions: [count][2*BCAP candidates]
-    char *host = nullptr;  // pinned mirror
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    char *ws = nullptr;        // device: workspaces of the large searches
+    size_t ws_bytes = 0;
+    char *dev = nullptr;       // device: descriptors + outputs
+    size_t dev_bytes = 0;
+    char *host = nullptr;      // pinned: descriptor staging
+    size_t host_bytes = 0;
+    char *outd = nullptr;      // device: counts, candidates, summary of every slot
+    size_t outd_bytes = 0;
+    char *hsum = nullptr;      // pinned: summary copy
+    size_t hsum_bytes = 0;
+    std::string sig;           // shape of the captured graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t replays = 0, captures = 0;
 };
 
+static void drop_graph(BatchState *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->sig.clear();
+}
+
 void batch_release(rfr_ctx *ctx) {
-    if (!ctx->batch) return;
-    if (ctx->batch->dev) (void)hipFree(ctx->batch->dev);
-    if (ctx->batch->host) (void)hipHostFree(ctx->batch->host);
-    delete ctx->batch;
+    BatchState *b = ctx->batch;
+    if (!b) return;
+    drop_graph(b);
+    if (b->ws) (void)hipFree(b->ws);
+    if (b->dev) (void)hipFree(b->dev);
+    if (b->host) (void)hipHostFree(b->host);
+    if (b->outd) (void)hipFree(b->outd);
+    if (b->hsum) (void)hipHostFree(b->hsum);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->join) (void)hipEventDestroy(b->join);
+    if (b->side) (void)hipStreamDestroy(b->side);
+    delete b;
     ctx->batch = nullptr;
 }
 
-static rfr_status batch_init(rfr_ctx *ctx) {
-    if (ctx->batch) return RFR_OK;
-    BatchState *b = new BatchState();
-    if (hipMalloc(&b->dev, WAVE * REGION) != hipSuccess ||
-        hipHostMalloc(&b->host, WAVE * REGION, hipHostMallocDefault) != hipSuccess) {
-        ctx->batch = b;
-        batch_release(ctx);
-        return fail(RFR_ENOMEM, "batch candidate buffers");
+static rfr_status grow(char **p, size_t *have, size_t need, bool pinned, BatchState *b) {
+    if (*have >= need) return RFR_OK;
+    drop_graph(b);  // the graph holds the old addresses
+    if (*p) (void)(pinned ? hipHostFree(*p) : hipFree(*p));
+    *p = nullptr;
+    *have = 0;
+    size_t sz = need + need / 4;
+    hipError_t e = pinned ? hipHostMalloc((void **)p, sz, hipHostMallocDefault) : hipMalloc((void **)p, sz);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(RFR_ENOMEM, "batch buffer allocation failed");
     }
-    ctx->batch = b;
+    *have = sz;
     return RFR_OK;
+}
+
+// Copy each job's count and first HEAD pattern pairs into one compact summary.
+__global__ void k_summary(const uint64_t *counts, const uint64_t *cand, uint64_t stride, int njobs,
+                          uint64_t *summary) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= njobs) return;
+    uint64_t *s = summary + (size_t)j * SUMMARY;
+    const uint64_t c = counts[j];
+    s[0] = c;
+    const uint64_t *src = cand + (size_t)j * stride;
+    const uint64_t k = c < HEAD ? c : HEAD;
+    for (uint64_t i = 0; i < 2 * k; ++i) s[1 + i] = src[i];
 }
 
 // Profiling: events of one search, and accumulation after it completed.
@@ -71,12 +123,44 @@ void profile_collect(rfr_ctx *ctx, int k, int n) {
     int na, nb;
     split_halves(n, na, nb);
     ctx->prof.searches += 1;
+    ctx->prof.launches += 1;
     ctx->prof.keys += (1ull << na) + (1ull << nb);
+}
+
+static void to_pat(const uint64_t *pair, int na, int nb, Pat &p) {
+    for (int b = 0; b < na; ++b)
+        if ((pair[0] >> b) & 1) p.set(b);
+    for (int b = 0; b < nb; ++b)
+        if ((pair[1] >> b) & 1) p.set(na + b);
 }
 
 }  // namespace rfr
 
 using namespace rfr;
+
+// One device pass of the mid-size and small searches (descriptors already
+// staged): uploaded, both paths on two streams, summary of all slots, copy back.
+static bool device_pass(BatchState *B, hipStream_t S0, size_t desc_bytes, size_t o_jobs, size_t o_bases,
+                        size_t o_small, size_t o_queue, const MultiLaunch &ML, int nS, StageEvents *ev,
+                        const uint64_t *counts_d, const uint64_t *cand_d, uint64_t *sum_d, uint64_t *sum_h,
+                        int nslots) {
+    bool ok = hipMemcpyAsync(B->dev, B->host, desc_bytes, hipMemcpyHostToDevice, S0) == hipSuccess;
+    ok = ok && hipEventRecord(B->fork, S0) == hipSuccess;
+    ok = ok && hipStreamWaitEvent(B->side, B->fork, 0) == hipSuccess;
+    ok = ok && launch_small((const SmallJob *)(B->dev + o_small), nS, (uint32_t *)(B->dev + o_queue),
+                            std::min(nS, 1024), B->side) == hipSuccess;
+    ok = ok && ML.launch((const dev::JobArgs *)(B->dev + o_jobs), (const uint32_t *)(B->dev + o_bases), S0, ev) ==
+                   hipSuccess;
+    ok = ok && hipEventRecord(B->join, B->side) == hipSuccess;
+    ok = ok && hipStreamWaitEvent(S0, B->join, 0) == hipSuccess;
+    if (ok) {
+        hipLaunchKernelGGL(k_summary, dim3((nslots + 255) / 256), dim3(256), 0, S0, counts_d, cand_d,
+                           (uint64_t)2 * BCAP, nslots, sum_d);
+        ok = hipGetLastError() == hipSuccess;
+    }
+    ok = ok && hipMemcpyAsync(sum_h, sum_d, (size_t)nslots * SUMMARY * 8, hipMemcpyDeviceToHost, S0) == hipSuccess;
+    return ok;
+}
 
 extern "C" rfr_status rfr_factor_batch(rfr_ctx *ctx, int count, const int64_t *coeffs, const int32_t *degrees,
                                        rfr_result **out, rfr_status *status) {
@@ -89,146 +173,266 @@ extern "C" rfr_status rfr_factor_batch(rfr_ctx *ctx, int count, const int64_t *c
         if (degrees[i] < 1 || degrees[i] > RFR_MAX_DEGREE) return fail(RFR_EINVAL, "degree out of range");
         off[i + 1] = off[i] + (size_t)degrees[i] + 1;
     }
-    rfr_status bst = batch_init(ctx);
-    if (bst != RFR_OK) return bst;
-    std::vector<int> order(count);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return degrees[a] > degrees[b]; });
+    if (!ctx->batch) {
+        BatchState *b = new BatchState();
+        if (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess) {
+            ctx->batch = b;
+            batch_release(ctx);
+            return fail(RFR_EDEVICE, "batch stream/event creation failed");
+        }
+        ctx->batch = b;
+    }
+    BatchState *B = ctx->batch;
+    const int nthreads = (int)std::min<unsigned>(std::max(1u, std::thread::hardware_concurrency()), 16u);
+    hipStream_t S0 = ctx->main.stream;
 
+    // output slots: slot k belongs to the k-th polynomial in largest-first order
+    //   counts[count] | cand[count][2*BCAP] | summary[count][SUMMARY]
+    const size_t o_cand = ((size_t)8 * count + 255) & ~(size_t)255;
+    const size_t o_sum = o_cand + (size_t)count * 2 * BCAP * 8;
+    rfr_status e0 = grow(&B->outd, &B->outd_bytes, o_sum + (size_t)count * SUMMARY * 8, false, B);
+    if (e0 == RFR_OK) e0 = grow(&B->hsum, &B->hsum_bytes, (size_t)count * SUMMARY * 8, true, B);
+    if (e0 != RFR_OK) return e0;
+    uint64_t *counts_d = (uint64_t *)B->outd;
+    uint64_t *cand_d = (uint64_t *)(B->outd + o_cand);
+    uint64_t *sum_d = (uint64_t *)(B->outd + o_sum);
+    uint64_t *sum_h = (uint64_t *)B->hsum;
+
+    // ---- 1. host stage on the pool, largest first; the device thread below
+    //         consumes the results as they become ready
     std::vector<Prepared> P(count);
     std::vector<rfr_status> st(count, RFR_OK);
     std::vector<std::string> err(count);
+    std::vector<int> order(count), slot(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return degrees[a] > degrees[b]; });
+    for (int k = 0; k < count; ++k) slot[order[k]] = k;
     std::vector<std::atomic<int>> ready(count);
     for (auto &r : ready) r.store(0);
-    std::vector<std::vector<Pat>> cands(count);
-
-    const int nthreads = (int)std::min<unsigned>(std::max(1u, std::thread::hardware_concurrency()), 16u);
     std::atomic<int> next{0};
-    auto prep_work = [&]() {
-        for (;;) {
-            int k = next.fetch_add(1);
-            if (k >= count) break;
-            int i = order[k];
-            st[i] = prepare(coeffs + off[i], degrees[i], P[i], err[i]);
-            ready[i].store(1, std::memory_order_release);
-        }
-    };
     std::vector<std::thread> pool;
-    for (int t = 0; t < nthreads; ++t) pool.emplace_back(prep_work);
+    for (int t = 0; t < nthreads; ++t)
+        pool.emplace_back([&] {
+            for (int k; (k = next.fetch_add(1)) < count;) {
+                const int i = order[k];
+                st[i] = prepare(coeffs + off[i], degrees[i], P[i], err[i]);
+                ready[i].store(1, std::memory_order_release);
+            }
+        });
 
-    Slot &s = ctx->main;
-    BatchState *B = ctx->batch;
+    // ---- 2. huge searches are queued on the stream as soon as their roots are
+    //         ready (each fills the GPU on its own); the rest is classified
+    std::vector<int> huge, large, small;
     rfr_status dev_st = RFR_OK;
-    std::vector<int> wave;
-    for (int w0 = 0; w0 < count && dev_st == RFR_OK; w0 += WAVE) {
-        wave.clear();
-        const int w1 = std::min(count, w0 + WAVE);
-        for (int k = w0; k < w1; ++k) {
-            const int i = order[k];
-            while (!ready[i].load(std::memory_order_acquire)) std::this_thread::yield();
-            if (st[i] != RFR_OK || P[i].n <= 1) continue;
-            if (P[i].n > 2 * dev::MAX_HALF + 1) {
-                st[i] = RFR_EOVERFLOW;
-                err[i] = "too many elements for the search tables";
-                continue;
-            }
-            const size_t need = recombine_workspace(P[i].n);
-            if (need > s.ws_bytes) {
-                // growing the workspace: earlier searches of this wave still use it
-                if (hipStreamSynchronize(s.stream) != hipSuccess) {
-                    dev_st = fail(RFR_EDEVICE, "device search failed");
-                    break;
-                }
-                rfr_status e = ensure_workspace(ctx, s, need);
-                if (e != RFR_OK) {
-                    st[i] = e;
-                    err[i] = g_last_error;
-                    continue;
-                }
-            }
-            const int slot = (int)wave.size();
-            char *dreg = B->dev + (size_t)slot * REGION;
-            std::string e2;
-            rfr_status e = enqueue_recombine(P[i].w.data(), P[i].n, P[i].t_lo, P[i].t_hi, s.ws, s.ws_bytes,
-                                             s.stream, (uint64_t *)(dreg + 8), BCAP, (uint64_t *)dreg,
-                                             profile_events(ctx, slot), e2);
-            if (e != RFR_OK) {
-                st[i] = e;
-                err[i] = e2;
-                continue;
-            }
-            if (hipMemcpyAsync(B->host + (size_t)slot * REGION, dreg, 8 + HEAD * 16, hipMemcpyDeviceToHost,
-                               s.stream) != hipSuccess) {
-                dev_st = fail(RFR_EDEVICE, "candidate copy failed");
+    for (int k = 0; k < count && dev_st == RFR_OK; ++k) {
+        const int i = order[k];
+        while (!ready[i].load(std::memory_order_acquire)) std::this_thread::yield();
+        if (st[i] != RFR_OK || P[i].n <= 1) continue;
+        if (P[i].n > 2 * dev::MAX_HALF + 1) {
+            st[i] = RFR_EOVERFLOW;
+            err[i] = "too many elements for the search tables";
+            continue;
+        }
+        int na, nb;
+        split_halves(P[i].n, na, nb);
+        if (na <= SMALL_HALF) {
+            small.push_back(i);
+            continue;
+        }
+        if (na < HUGE_HALF) {
+            large.push_back(i);
+            continue;
+        }
+        const size_t need = recombine_workspace(P[i].n);
+        if (need > ctx->main.ws_bytes) {
+            if (hipStreamSynchronize(S0) != hipSuccess) {
+                dev_st = fail(RFR_EDEVICE, "device search failed");
                 break;
             }
-            wave.push_back(i);
-        }
-        if (dev_st != RFR_OK) break;
-        if (hipStreamSynchronize(s.stream) != hipSuccess) {
-            dev_st = fail(RFR_EDEVICE, "device search failed");
-            break;
-        }
-        for (int slot = 0; slot < (int)wave.size(); ++slot) {
-            const int i = wave[slot];
-            profile_collect(ctx, slot, P[i].n);
-            char *hreg = B->host + (size_t)slot * REGION;
-            uint64_t cnt = *(uint64_t *)hreg;
-            if (cnt == ~0ull) {
-                // more than a wave region holds: redo with the full capacity
-                rfr_status e = search_on_slot(ctx, s, P[i], cands[i]);
-                if (e != RFR_OK) {
-                    st[i] = e;
-                    err[i] = g_last_error;
-                }
+            rfr_status e = ensure_workspace(ctx, ctx->main, need);
+            if (e != RFR_OK) {
+                st[i] = e;
+                err[i] = g_last_error;
                 continue;
             }
-            if (cnt > HEAD) {
-                if (hipMemcpy(hreg + 8, B->dev + (size_t)slot * REGION + 8, cnt * 16, hipMemcpyDeviceToHost) !=
-                    hipSuccess) {
-                    dev_st = fail(RFR_EDEVICE, "candidate copy failed");
-                    break;
-                }
-            }
-            const uint64_t *hc = (const uint64_t *)(hreg + 8);
-            int na, nb;
-            split_halves(P[i].n, na, nb);
-            cands[i].resize(cnt);
-            for (uint64_t c = 0; c < cnt; ++c) {
-                Pat p;
-                for (int b = 0; b < na; ++b)
-                    if ((hc[2 * c] >> b) & 1) p.set(b);
-                for (int b = 0; b < nb; ++b)
-                    if ((hc[2 * c + 1] >> b) & 1) p.set(na + b);
-                cands[i][c] = p;
-            }
         }
+        std::string e2;
+        rfr_status e = enqueue_recombine(P[i].w.data(), P[i].n, P[i].t_lo, P[i].t_hi, ctx->main.ws,
+                                         ctx->main.ws_bytes, S0, cand_d + (size_t)k * 2 * BCAP, BCAP,
+                                         counts_d + k, profile_events(ctx, 1 + (int)huge.size()), e2);
+        if (e != RFR_OK) {
+            st[i] = e;
+            err[i] = e2;
+            continue;
+        }
+        huge.push_back(i);
     }
     for (auto &t : pool) t.join();
     if (dev_st != RFR_OK) return dev_st;
+    const int nL = (int)large.size(), nS = (int)small.size();
 
-    // confirmation and packing on the pool
-    next.store(0);
-    auto conf_work = [&]() {
-        for (;;) {
-            int k = next.fetch_add(1);
-            if (k >= count) break;
-            int i = order[k];
-            out[i] = nullptr;
-            if (st[i] == RFR_OK) {
-                Factored F;
-                if (P[i].n <= 1) trivial_factor(P[i], F);
-                else st[i] = confirm_and_factor(P[i], cands[i], F, err[i]);
-                if (st[i] == RFR_OK) {
-                    out[i] = pack_result(P[i], F);
-                    if (!out[i]) st[i] = RFR_ENOMEM;
-                }
+    // ---- 3. layout of the mid-size searches and the descriptors
+    std::vector<JobPlan> plans(nL);
+    std::vector<size_t> wsoff(nL + 1, 0);
+    for (int k = 0; k < nL; ++k) {
+        int na, nb;
+        split_halves(P[large[k]].n, na, nb);
+        size_t bts = plan_job(na, nb, plans[k], BCAP + 1);
+        wsoff[k + 1] = wsoff[k] + ((bts + 255) & ~(size_t)255);
+    }
+    // descriptor block: JobArgs[nL] | bases | SmallJob[nS] | queue counter
+    const size_t o_jobs = 0;
+    const size_t o_bases = (o_jobs + sizeof(dev::JobArgs) * nL + 255) & ~(size_t)255;
+    const size_t bases_bytes = (size_t)dev::NSTAGES * (nL + 1) * 4;
+    const size_t o_small = (o_bases + bases_bytes + 255) & ~(size_t)255;
+    const size_t o_queue = (o_small + sizeof(SmallJob) * nS + 255) & ~(size_t)255;
+    const size_t desc_bytes = o_queue + 256;
+    rfr_status e = grow(&B->ws, &B->ws_bytes, std::max<size_t>(wsoff[nL], 256), false, B);
+    if (e == RFR_OK) e = grow(&B->dev, &B->dev_bytes, desc_bytes, false, B);
+    if (e == RFR_OK) e = grow(&B->host, &B->host_bytes, desc_bytes, true, B);
+    if (e != RFR_OK) return e;
+    MultiLaunch ML;
+    for (int k = 0; k < nL; ++k) {
+        const Prepared &Q = P[large[k]];
+        const int sk = slot[large[k]];
+        int na, nb;
+        split_halves(Q.n, na, nb);
+        std::vector<uint64_t> wneg(nb);
+        for (int t = 0; t < nb; ++t) wneg[t] = 0 - Q.w[na + t];
+        dev::JobArgs J;
+        build_job(plans[k], B->ws + wsoff[k], Q.w.data(), wneg.data(), Q.t_lo, Q.t_hi,
+                  cand_d + (size_t)sk * 2 * BCAP, counts_d + sk, BCAP, J);
+        ML.add(plans[k], J);
+    }
+    if (nL) {
+        std::memcpy(B->host + o_jobs, ML.jobs.data(), sizeof(dev::JobArgs) * nL);
+        ML.pack_bases((uint32_t *)(B->host + o_bases));
+    }
+    SmallJob *sj = (SmallJob *)(B->host + o_small);
+    for (int k = 0; k < nS; ++k) {
+        const Prepared &Q = P[small[k]];
+        const int sk = slot[small[k]];
+        SmallJob S{};
+        split_halves(Q.n, S.na, S.nb);
+        for (int t = 0; t < Q.n - 1; ++t) S.w[t] = Q.w[t];
+        S.t_lo = Q.t_lo;
+        S.t_hi = Q.t_hi;
+        S.out = cand_d + (size_t)sk * 2 * BCAP;
+        S.out_count = counts_d + sk;
+        S.cap = BCAP;
+        sj[k] = S;
+    }
+
+    // ---- 4. the device pass: captured once per shape into a graph and
+    //         replayed; when profiling, launched directly with stage events
+    if (ctx->profiling) {
+        StageEvents *ev = nL ? profile_events(ctx, 0) : nullptr;
+        if (!device_pass(B, S0, desc_bytes, o_jobs, o_bases, o_small, o_queue, ML, nS, ev, counts_d, cand_d, sum_d,
+                         sum_h, count) ||
+            hipStreamSynchronize(S0) != hipSuccess)
+            return fail(RFR_EDEVICE, "batch device pass failed");
+        for (size_t h = 0; h < huge.size(); ++h) profile_collect(ctx, 1 + (int)h, P[huge[h]].n);
+        if (nL) {
+            for (int i = 0; i < 6; ++i) {
+                float ms = 0;
+                if (hipEventElapsedTime(&ms, (hipEvent_t)ev->ev[i], (hipEvent_t)ev->ev[i + 1]) == hipSuccess)
+                    ctx->prof.stage_ms[i] += ms;
             }
-            status[i] = st[i];
+            ctx->prof.searches += nL;
+            ctx->prof.launches += 1;
+            for (int k = 0; k < nL; ++k) {
+                int na, nb;
+                split_halves(P[large[k]].n, na, nb);
+                ctx->prof.keys += (1ull << na) + (1ull << nb);
+            }
         }
+    } else {
+        std::ostringstream sig;
+        sig << count << ':' << nL << ':' << nS << ':' << (void *)B->ws << ':' << (void *)B->dev << ':'
+            << (void *)B->host << ':' << (void *)B->outd << ':' << (void *)B->hsum << ':' << desc_bytes << ':'
+            << ML.maxB1 << ':' << ML.maxB2;
+        if (nL)
+            for (int s = 0; s < dev::NSTAGES; ++s) sig << ':' << ML.bases[s].back();
+        if (!B->exec || B->sig != sig.str()) {
+            drop_graph(B);
+            bool ok = hipStreamBeginCapture(S0, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            ok = ok && device_pass(B, S0, desc_bytes, o_jobs, o_bases, o_small, o_queue, ML, nS, nullptr, counts_d,
+                                   cand_d, sum_d, sum_h, count);
+            hipGraph_t g = nullptr;
+            hipError_t ec = hipStreamEndCapture(S0, &g);
+            if (!ok || ec != hipSuccess || !g) {
+                if (g) (void)hipGraphDestroy(g);
+                return fail(RFR_EDEVICE, "batch graph capture failed");
+            }
+            B->graph = g;
+            if (hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+                B->exec = nullptr;
+                drop_graph(B);
+                return fail(RFR_EDEVICE, "batch graph instantiation failed");
+            }
+            B->sig = sig.str();
+            ++B->captures;
+        } else {
+            ++B->replays;
+        }
+        if (hipGraphLaunch(B->exec, S0) != hipSuccess || hipStreamSynchronize(S0) != hipSuccess)
+            return fail(RFR_EDEVICE, "batch device pass failed");
+    }
+
+    // ---- 5. candidates of every searched polynomial
+    std::vector<std::vector<Pat>> cands(count);
+    auto take = [&](int i) -> rfr_status {
+        const int k = slot[i];
+        const uint64_t *s = sum_h + (size_t)k * SUMMARY;
+        const uint64_t c = s[0];
+        int na, nb;
+        split_halves(P[i].n, na, nb);
+        if (c == ~0ull) {
+            // more candidates than a batch slot holds: redo with the full capacity
+            rfr_status r = search_on_slot(ctx, ctx->main, P[i], cands[i]);
+            if (r != RFR_OK) {
+                st[i] = r;
+                err[i] = g_last_error;
+            }
+            return RFR_OK;
+        }
+        cands[i].assign(c, Pat());
+        if (c <= HEAD) {
+            for (uint64_t q = 0; q < c; ++q) to_pat(s + 1 + 2 * q, na, nb, cands[i][q]);
+        } else {
+            std::vector<uint64_t> tmp(2 * c);
+            if (hipMemcpy(tmp.data(), cand_d + (size_t)k * 2 * BCAP, 16 * c, hipMemcpyDeviceToHost) != hipSuccess)
+                return fail(RFR_EDEVICE, "candidate copy failed");
+            for (uint64_t q = 0; q < c; ++q) to_pat(tmp.data() + 2 * q, na, nb, cands[i][q]);
+        }
+        return RFR_OK;
     };
+    for (auto *grp : {&huge, &large, &small})
+        for (int i : *grp)
+            if (take(i) != RFR_OK) return RFR_EDEVICE;
+
+    // ---- 6. confirmation and packing on the pool
+    next.store(0);
     pool.clear();
-    for (int t = 0; t < nthreads; ++t) pool.emplace_back(conf_work);
+    for (int t = 0; t < nthreads; ++t)
+        pool.emplace_back([&] {
+            for (int k; (k = next.fetch_add(1)) < count;) {
+                const int i = order[k];
+                out[i] = nullptr;
+                if (st[i] == RFR_OK) {
+                    Factored F;
+                    if (P[i].n <= 1) trivial_factor(P[i], F);
+                    else st[i] = confirm_and_factor(P[i], cands[i], F, err[i]);
+                    if (st[i] == RFR_OK) {
+                        out[i] = pack_result(P[i], F);
+                        if (!out[i]) st[i] = RFR_ENOMEM;
+                    }
+                }
+                status[i] = st[i];
+            }
+        });
     for (auto &t : pool) t.join();
     for (int i = 0; i < count; ++i)
         if (status[i] != RFR_OK && !err[i].empty()) g_last_error = err[i];
@@ -245,5 +449,7 @@ extern "C" rfr_status rfr_profile(rfr_ctx *ctx, int enable) {
 extern "C" rfr_status rfr_profile_read(rfr_ctx *ctx, rfr_profile_t *out) {
     if (!ctx || !out) return fail(RFR_EINVAL, "NULL argument");
     *out = ctx->prof;
+    out->graph_captures = ctx->batch ? ctx->batch->captures : 0;
+    out->graph_replays = ctx->batch ? ctx->batch->replays : 0;
     return RFR_OK;
 }

@@ -66,6 +66,7 @@ struct rfr_ctx {
     rfr_profile_t prof{};
     std::vector<hipEvent_t> prof_ev;
     std::vector<rfr::StageEvents> prof_se;
+    uint64_t prof_graph_replays = 0, prof_graph_captures = 0;
 };
 
 namespace rfr {

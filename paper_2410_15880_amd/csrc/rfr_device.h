@@ -18,13 +18,13 @@ constexpr int NT1 = 256;          // threads per workgroup
 constexpr int KPT1 = 16;          // Gray steps (keys per thread) per LDS tile
 constexpr int T1 = NT1 * KPT1;    // keys per K1 tile (32 KB of LDS)
 constexpr int TILES1 = 8;         // tiles per K0/K1 workgroup
-constexpr int MAXB1_LOG = 10;     // level-1 digit bits (buckets) at most
+constexpr int MAXB1_LOG = 11;     // level-1 digit bits (buckets) at most
 constexpr int MAXB1 = 1 << MAXB1_LOG;
 // ---- K2: per-bucket tile sort by the level-2 digit
 constexpr int NT2 = 512;
 constexpr int T2 = 4096;          // keys per tile (<= 65535: u16 digit offsets)
 constexpr int KPT2 = T2 / NT2;
-constexpr int MAXB2_LOG = 10;
+constexpr int MAXB2_LOG = 12;
 constexpr int MAXB2 = 1 << MAXB2_LOG;
 // ---- K3: sub-bucket gather, LDS radix sort of B', band join probing it with A
 constexpr int NT3 = 256;
@@ -71,7 +71,23 @@ struct JobArgs {
     uint64_t cap;
     uint32_t *flags;            // bit 0: sort overflow, bit 1: join fallback used
 };
+
+// Stages of the pipeline (kernel launches), in launch order.
+enum Stage { ST_INIT, ST_COUNT, ST_COLS, ST_BUCKETS, ST_ENUM, ST_TILE2, ST_JOIN, ST_RFEW, ST_RMANY, ST_PAIRS, NSTAGES };
+
+// Batch of jobs in device memory (see pick() in rfr_device.hip).
+struct Multi {
+    const JobArgs *jobs;
+    const uint32_t *bases;  // [NSTAGES][njobs + 1]
+    int njobs;
+};
 }  // namespace dev
+
+// Optional events recorded between stages (any entry may be null):
+// 0 start, 1 after count, 2 after scans, 3 after K1, 4 after K2, 5 after K3, 6 end.
+struct StageEvents {
+    void *ev[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+};
 
 struct HalfPlan {
     int m = 0, L = 0;
@@ -84,17 +100,40 @@ struct JobPlan {
     int nhalves = 2;
     HalfPlan h[2];
     int B1 = 0, B2 = 0;
+    uint64_t kcap = dev::KCAP_MAX;
     uint64_t *kp = nullptr, *rec = nullptr, *counters = nullptr;
 };
 
-// Optional events recorded between stages (any entry may be null):
-// 0 start, 1 after count, 2 after scans, 3 after K1, 4 after K2, 5 after K3, 6 end.
-struct StageEvents {
-    void *ev[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+// Many searches launched stage by stage (one launch per stage for all jobs).
+struct MultiLaunch {
+    std::vector<dev::JobArgs> jobs;
+    std::vector<std::vector<uint32_t>> bases;  // [stage][job + 1]
+    int maxB1 = 0, maxB2 = 0;
+    void add(const JobPlan &P, const dev::JobArgs &J);
+    size_t bases_bytes() const;
+    void pack_bases(uint32_t *dst) const;
+    hipError_t launch(const dev::JobArgs *jobs_dev, const uint32_t *bases_dev, hipStream_t st,
+                      StageEvents *ev = nullptr) const;
 };
 
+// A search small enough for one workgroup's LDS (both halves <= 2^SMALL_HALF).
+constexpr int SMALL_HALF = 11;
+struct SmallJob {
+    uint64_t w[2 * SMALL_HALF];  // the n-1 searched weights
+    int na, nb;
+    uint64_t t_lo, t_hi;
+    uint64_t *out;        // [2*cap] pattern pairs
+    uint64_t *out_count;  // count, or ~0 on overflow
+    uint64_t cap;
+};
+
+
 // Workspace bytes for a search of half sizes (na, nb); nb < 0 = one half only.
-uint64_t plan_job(int na, int nb, JobPlan &P);
+uint64_t plan_job(int na, int nb, JobPlan &P, uint64_t kcap);
+// Lay the job out at ws and fill its kernel arguments (B' weights negated).
+void build_job(JobPlan &P, char *ws, const uint64_t *wa, const uint64_t *wb, uint64_t t_lo, uint64_t t_hi,
+               uint64_t *out, uint64_t *out_count, uint64_t cap, dev::JobArgs &J);
+hipError_t launch_small(const SmallJob *jobs_dev, int njobs, uint32_t *queue_dev, int grid, hipStream_t st);
 size_t recombine_workspace(int n);
 size_t expand_workspace(int m);
 

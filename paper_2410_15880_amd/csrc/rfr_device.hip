@@ -111,8 +111,39 @@ __device__ __forceinline__ void emit_pair(const JobArgs &J, uint64_t a, uint64_t
     }
 }
 
+// ------------------------------------------------------------------ job selection
+// A launch serves one search (MULTI = false: the job is the kernel argument)
+// or every search of a batch (MULTI = true: M.jobs in device memory and, per
+// stage, M.bases[stage][0..njobs] the first block of each job, so block x
+// belongs to job j with bases[j] <= x < bases[j+1]).
+template <bool MULTI>
+__device__ __forceinline__ bool pick(const JobArgs &arg, const Multi &M, int stage, const JobArgs *&J, uint32_t &bx) {
+    if (!MULTI) {
+        J = &arg;
+        bx = blockIdx.x;
+        return true;
+    }
+    const uint32_t *base = M.bases + (size_t)stage * (M.njobs + 1);
+    const uint32_t x = blockIdx.x;
+    if (x >= base[M.njobs]) return false;
+    int lo = 0, hi = M.njobs - 1;  // last j with base[j] <= x
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (base[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    J = M.jobs + lo;
+    bx = x - base[lo];
+    return true;
+}
+
 // ------------------------------------------------------------------ init
-__global__ void k_init(JobArgs J) {
+template <bool MULTI>
+__global__ void k_init(JobArgs Jarg, Multi M) {
+    const JobArgs *Jp;
+    uint32_t bx;
+    if (!pick<MULTI>(Jarg, M, ST_INIT, Jp, bx)) return;
+    const JobArgs &J = *Jp;
     if (threadIdx.x == 0) {
         *J.kp_count = 0;
         J.rec_count[0] = 0;
@@ -127,10 +158,13 @@ __global__ void k_init(JobArgs J) {
 // low L pattern bits (its partial sum is fixed); step h selects the high bits
 // gray(h) = h ^ (h >> 1), so going from h to h+1 flips exactly bit ctz(h+1) and
 // changes the high sum by one wavefront-uniform +-w.
-template <bool COUNT, int NBMAX>
-__global__ __launch_bounds__(NT1) void k_enum(JobArgs J) {
+template <bool COUNT, int NBMAX, bool MULTI>
+__global__ __launch_bounds__(NT1) void k_enum(JobArgs Jarg, Multi M) {
+    const JobArgs *Jp;
+    uint32_t wg;
+    if (!pick<MULTI>(Jarg, M, COUNT ? ST_COUNT : ST_ENUM, Jp, wg)) return;
+    const JobArgs &J = *Jp;
     const HalfArgs &H = J.h[blockIdx.y];
-    const uint32_t wg = blockIdx.x;
     if (wg >= H.nwg1) return;
     const int B1 = J.B1;
     const int nb = 1 << B1;
@@ -229,9 +263,14 @@ __global__ __launch_bounds__(NT1) void k_enum(JobArgs J) {
 // ------------------------------------------------------------------ S1 / S2
 // Column prefix: hist1[b][w] becomes the exclusive prefix over w; the bucket
 // total goes to bstart[b] (turned into bucket starts by S2).
-__global__ __launch_bounds__(NT1) void k_scan_cols(JobArgs J) {
+template <bool MULTI>
+__global__ __launch_bounds__(NT1) void k_scan_cols(JobArgs Jarg, Multi M) {
+    const JobArgs *Jp;
+    uint32_t bx;
+    if (!pick<MULTI>(Jarg, M, ST_COLS, Jp, bx)) return;
+    const JobArgs &J = *Jp;
     const HalfArgs &H = J.h[blockIdx.y];
-    const int b = blockIdx.x;
+    const int b = (int)bx;
     if (b >= (1 << J.B1)) return;
     __shared__ uint64_t s_tmp[NT1 / 64 + 1];
     uint64_t *col = H.hist1 + (size_t)b * H.nwg1;
@@ -247,7 +286,12 @@ __global__ __launch_bounds__(NT1) void k_scan_cols(JobArgs J) {
     if (threadIdx.x == 0) H.bstart[b] = carry;
 }
 
-__global__ __launch_bounds__(NT1) void k_scan_buckets(JobArgs J) {
+template <bool MULTI>
+__global__ __launch_bounds__(NT1) void k_scan_buckets(JobArgs Jarg, Multi M) {
+    const JobArgs *Jp;
+    uint32_t bx;
+    if (!pick<MULTI>(Jarg, M, ST_BUCKETS, Jp, bx)) return;
+    const JobArgs &J = *Jp;
     const HalfArgs &H = J.h[blockIdx.y];
     const int nb = 1 << J.B1;
     __shared__ uint64_t s_tmp[NT1 / 64 + 1];
@@ -276,11 +320,14 @@ __global__ __launch_bounds__(NT1) void k_scan_buckets(JobArgs J) {
 // One tile (<= T2 keys) of one level-1 bucket: counting sort by the level-2
 // digit in LDS, written back in place; digstart[d][tile] = offset of digit d
 // inside the tile, digstart[nd][tile] = tile length.
-template <int NBMAX>
-__global__ __launch_bounds__(NT2) void k_tile2(JobArgs J) {
+template <int NBMAX, bool MULTI>
+__global__ __launch_bounds__(NT2) void k_tile2(JobArgs Jarg, Multi M) {
+    const JobArgs *Jp;
+    uint32_t tile;
+    if (!pick<MULTI>(Jarg, M, ST_TILE2, Jp, tile)) return;
+    const JobArgs &J = *Jp;
     const HalfArgs &H = J.h[blockIdx.y];
     const int nb = 1 << J.B1;
-    const uint32_t tile = blockIdx.x;
     const uint32_t ntiles = H.tstart[nb];
     if (tile >= ntiles) return;
     const int nd = 1 << J.B2;
@@ -530,12 +577,15 @@ __device__ void join_fallback(const JobArgs &J, uint32_t s, uint32_t NS, int b, 
 //     [a - t_hi, a + t_lo] overlaps inside the sub-bucket and emits every b'
 //     in it; a window reaching past the sub-bucket (or wrapping past 0) also
 //     scans the neighbour sub-bucket of B' from global memory (edge_scan).
-template <bool SORT_OUT>
-__global__ __launch_bounds__(NT3) void k_join(JobArgs J, uint64_t *sorted_out) {
+template <bool SORT_OUT, bool MULTI>
+__global__ __launch_bounds__(NT3) void k_join(JobArgs Jarg, Multi M, uint64_t *sorted_out) {
     constexpr int NH = SORT_OUT ? 1 : 2;
+    const JobArgs *Jp;
+    uint32_t s;
+    if (!pick<MULTI>(Jarg, M, ST_JOIN, Jp, s)) return;
+    const JobArgs &J = *Jp;
     const int LB = J.B1 + J.B2;
     const uint32_t NS = 1u << LB;
-    uint32_t s = blockIdx.x;
     if (s >= NS) return;
     if (NS >= 64) s = (s & 7) * (NS >> 3) + (s >> 3);
     const int b = (int)(s >> J.B2), d = (int)(s & ((1u << J.B2) - 1));
@@ -613,15 +663,20 @@ __global__ __launch_bounds__(NT3) void k_join(JobArgs J, uint64_t *sorted_out) {
 // the high ones.  The 2^L low sums are sorted once in LDS; then every Gray step
 // h needs, per candidate key K, one binary search for K - shi(g) among them
 // (a meet in the middle inside the half) instead of 2^L enumerated keys.
-__global__ __launch_bounds__(NT1) void k_recover_few(JobArgs J) {
+template <bool MULTI>
+__global__ __launch_bounds__(NT1) void k_recover_few(JobArgs Jarg, Multi M) {
+    const JobArgs *Jp;
+    uint32_t bx;
+    if (!pick<MULTI>(Jarg, M, ST_RFEW, Jp, bx)) return;
+    const JobArgs &J = *Jp;
     const int half = blockIdx.y;
     const HalfArgs &H = J.h[half];
     const uint64_t cnt = *J.kp_count;
     if (cnt > RECOVER_FEW || cnt == 0) return;
     const int tid = threadIdx.x;
     const int nl = 1 << H.L;
-    const uint64_t h0 = ((uint64_t)blockIdx.x * NT1 + tid) * SPT4;
-    if ((uint64_t)blockIdx.x * NT1 * SPT4 >= H.steps) return;
+    const uint64_t h0 = ((uint64_t)bx * NT1 + tid) * SPT4;
+    if ((uint64_t)bx * NT1 * SPT4 >= H.steps) return;
 
     __shared__ uint64_t s_w[64];
     __shared__ uint64_t s_v[256], s_sorted[256];
@@ -688,10 +743,14 @@ __global__ __launch_bounds__(NT1) void k_recover_few(JobArgs J) {
 // Pattern recovery for many candidate keys: re-enumerate the half (same Gray
 // walk as K1, no stores) and look every key up in an LDS bitmap of candidate
 // key prefixes, confirming hits against the list.
-__global__ __launch_bounds__(NT1) void k_recover(JobArgs J) {
+template <bool MULTI>
+__global__ __launch_bounds__(NT1) void k_recover(JobArgs Jarg, Multi M) {
+    const JobArgs *Jp;
+    uint32_t wg;
+    if (!pick<MULTI>(Jarg, M, ST_RMANY, Jp, wg)) return;
+    const JobArgs &J = *Jp;
     const int half = blockIdx.y;
     const HalfArgs &H = J.h[half];
-    const uint32_t wg = blockIdx.x;
     if (wg >= H.nwg1) return;
     const uint64_t cnt = *J.kp_count;
     if (cnt > J.kcap || cnt <= RECOVER_FEW) return;
@@ -752,7 +811,12 @@ __global__ __launch_bounds__(NT1) void k_recover(JobArgs J) {
 
 // ------------------------------------------------------------------ K5
 // One workgroup: distinct key pairs x (patterns of each key) -> pattern pairs.
-__global__ __launch_bounds__(NT1) void k_pairs(JobArgs J) {
+template <bool MULTI>
+__global__ __launch_bounds__(NT1) void k_pairs(JobArgs Jarg, Multi M) {
+    const JobArgs *Jp;
+    uint32_t bx;
+    if (!pick<MULTI>(Jarg, M, ST_PAIRS, Jp, bx)) return;
+    const JobArgs &J = *Jp;
     const uint64_t cnt = *J.kp_count;
     __shared__ uint64_t s_total;
     if (threadIdx.x == 0) s_total = 0;
@@ -805,22 +869,25 @@ static void plan_half(int m, HalfPlan &h) {
     h.nwg1 = (uint32_t)((h.steps + h.spw - 1) / h.spw);
 }
 
+// Digit split of the 2^LB sub-buckets (mean 2^SUB_LOG keys of the larger half
+// each): up to 16 bits as 8 + 8 (level-1 runs of ~16 keys per K1 tile, level-2
+// runs of ~16 keys per K2 tile); beyond that both levels grow, level 1 first.
 static void plan_bits(uint64_t nmax, int &B1, int &B2) {
     int lg = 0;
     while ((1ull << lg) < nmax) ++lg;
     int LB = lg > SUB_LOG ? lg - SUB_LOG : 0;
+    if (LB > MAXB1_LOG + MAXB2_LOG) LB = MAXB1_LOG + MAXB2_LOG;
     if (LB <= 16) {
         B1 = LB < 8 ? LB : 8;
         B2 = LB - B1;
     } else {
-        B1 = (LB + 1) / 2;
-        B2 = LB / 2;
+        B1 = std::min(MAXB1_LOG, (LB + 1) / 2);
+        B2 = LB - B1;
     }
-    if (B1 > MAXB1_LOG) {
-        B2 += B1 - MAXB1_LOG;
-        B1 = MAXB1_LOG;
+    if (B2 > MAXB2_LOG) {
+        B1 += B2 - MAXB2_LOG;
+        B2 = MAXB2_LOG;
     }
-    if (B2 > MAXB2_LOG) B2 = MAXB2_LOG;
 }
 
 // Carve the workspace; returns bytes needed.  With base == nullptr only sizes.
@@ -848,14 +915,15 @@ static uint64_t layout(JobPlan &P, char *base) {
         h.a.m = h.m;
         h.a.L = h.L;
     }
-    P.kp = (uint64_t *)take(KCAP_MAX * 16);
-    P.rec = (uint64_t *)take(2ull * KCAP_MAX * 16);
+    P.kp = (uint64_t *)take(P.kcap * 16);
+    P.rec = (uint64_t *)take(2ull * P.kcap * 16);
     P.counters = (uint64_t *)take(64);
     return off;
 }
 
-uint64_t plan_job(int na, int nb, JobPlan &P) {
+uint64_t plan_job(int na, int nb, JobPlan &P, uint64_t kcap) {
     P = JobPlan();
+    P.kcap = kcap;
     P.nhalves = nb >= 0 ? 2 : 1;
     plan_half(na, P.h[0]);
     uint64_t nmax = P.h[0].N;
@@ -867,7 +935,8 @@ uint64_t plan_job(int na, int nb, JobPlan &P) {
     return layout(P, nullptr);
 }
 
-static void enqueue_common(JobPlan &P, char *ws, const uint64_t *wa, const uint64_t *wb, JobArgs &J) {
+void build_job(JobPlan &P, char *ws, const uint64_t *wa, const uint64_t *wb, uint64_t t_lo, uint64_t t_hi,
+               uint64_t *out, uint64_t *out_count, uint64_t cap, JobArgs &J) {
     layout(P, ws);
     J = JobArgs();
     J.B1 = P.B1;
@@ -883,33 +952,70 @@ static void enqueue_common(JobPlan &P, char *ws, const uint64_t *wa, const uint6
     J.rec = P.rec;
     J.rec_count = (uint32_t *)(P.counters + 1);
     J.flags = (uint32_t *)(P.counters + 2);
+    J.kcap = P.kcap;
+    J.t_lo = t_lo;
+    J.t_hi = t_hi;
+    J.out = out;
+    J.out_count = out_count;
+    J.cap = cap;
 }
 
-static hipError_t launch_front(JobPlan &P, JobArgs &J, hipStream_t st, StageEvents *ev) {
-    const int nh = P.nhalves;
+// Blocks (x) of every stage for one job; the y dimension is the half.
+void stage_blocks(const JobPlan &P, uint32_t *x) {
     uint32_t mw = 0;
-    uint64_t mt = 0;
-    for (int k = 0; k < nh; ++k) {
+    uint64_t mt = 0, ms = 0;
+    for (int k = 0; k < P.nhalves; ++k) {
         mw = std::max(mw, P.h[k].nwg1);
         mt = std::max<uint64_t>(mt, P.h[k].ntile2_max);
+        ms = std::max(ms, P.h[k].steps);
     }
+    x[ST_INIT] = 1;
+    x[ST_COUNT] = mw;
+    x[ST_COLS] = 1u << P.B1;
+    x[ST_BUCKETS] = 1;
+    x[ST_ENUM] = mw;
+    x[ST_TILE2] = (uint32_t)mt;
+    x[ST_JOIN] = 1u << (P.B1 + P.B2);
+    x[ST_RFEW] = (uint32_t)((ms + (uint64_t)NT1 * SPT4 - 1) / ((uint64_t)NT1 * SPT4));
+    x[ST_RMANY] = mw;
+    x[ST_PAIRS] = 1;
+}
+
+// All stages of a single-job or multi-job launch; with MULTI the grid of each
+// stage is grids[stage] and the per-job block offsets live in M.bases.
+template <bool MULTI>
+static hipError_t launch_all(const JobArgs &J, const Multi &M, const uint32_t *grids, int nh, int maxB1,
+                             int maxB2, bool search, uint64_t *sorted, hipStream_t st, StageEvents *ev) {
     auto rec = [&](int i) {
         if (ev && ev->ev[i]) (void)hipEventRecord((hipEvent_t)ev->ev[i], st);
     };
     rec(0);
-    hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, J);
-    if (P.B1 <= 8) hipLaunchKernelGGL((k_enum<true, 256>), dim3(mw, nh), dim3(NT1), 0, st, J);
-    else hipLaunchKernelGGL((k_enum<true, MAXB1>), dim3(mw, nh), dim3(NT1), 0, st, J);
+    hipLaunchKernelGGL((k_init<MULTI>), dim3(grids[ST_INIT]), dim3(64), 0, st, J, M);
+    if (maxB1 <= 8) hipLaunchKernelGGL((k_enum<true, 256, MULTI>), dim3(grids[ST_COUNT], nh), dim3(NT1), 0, st, J, M);
+    else if (maxB1 <= 10) hipLaunchKernelGGL((k_enum<true, 1024, MULTI>), dim3(grids[ST_COUNT], nh), dim3(NT1), 0, st, J, M);
+    else hipLaunchKernelGGL((k_enum<true, MAXB1, MULTI>), dim3(grids[ST_COUNT], nh), dim3(NT1), 0, st, J, M);
     rec(1);
-    hipLaunchKernelGGL(k_scan_cols, dim3(1 << P.B1, nh), dim3(NT1), 0, st, J);
-    hipLaunchKernelGGL(k_scan_buckets, dim3(1, nh), dim3(NT1), 0, st, J);
+    hipLaunchKernelGGL((k_scan_cols<MULTI>), dim3(grids[ST_COLS], nh), dim3(NT1), 0, st, J, M);
+    hipLaunchKernelGGL((k_scan_buckets<MULTI>), dim3(grids[ST_BUCKETS], nh), dim3(NT1), 0, st, J, M);
     rec(2);
-    if (P.B1 <= 8) hipLaunchKernelGGL((k_enum<false, 256>), dim3(mw, nh), dim3(NT1), 0, st, J);
-    else hipLaunchKernelGGL((k_enum<false, MAXB1>), dim3(mw, nh), dim3(NT1), 0, st, J);
+    if (maxB1 <= 8) hipLaunchKernelGGL((k_enum<false, 256, MULTI>), dim3(grids[ST_ENUM], nh), dim3(NT1), 0, st, J, M);
+    else if (maxB1 <= 10) hipLaunchKernelGGL((k_enum<false, 1024, MULTI>), dim3(grids[ST_ENUM], nh), dim3(NT1), 0, st, J, M);
+    else hipLaunchKernelGGL((k_enum<false, MAXB1, MULTI>), dim3(grids[ST_ENUM], nh), dim3(NT1), 0, st, J, M);
     rec(3);
-    if (P.B2 <= 8) hipLaunchKernelGGL((k_tile2<256>), dim3((uint32_t)mt, nh), dim3(NT2), 0, st, J);
-    else hipLaunchKernelGGL((k_tile2<MAXB2>), dim3((uint32_t)mt, nh), dim3(NT2), 0, st, J);
+    if (maxB2 <= 8) hipLaunchKernelGGL((k_tile2<256, MULTI>), dim3(grids[ST_TILE2], nh), dim3(NT2), 0, st, J, M);
+    else if (maxB2 <= 10) hipLaunchKernelGGL((k_tile2<1024, MULTI>), dim3(grids[ST_TILE2], nh), dim3(NT2), 0, st, J, M);
+    else hipLaunchKernelGGL((k_tile2<MAXB2, MULTI>), dim3(grids[ST_TILE2], nh), dim3(NT2), 0, st, J, M);
     rec(4);
+    if (!search) {
+        hipLaunchKernelGGL((k_join<true, MULTI>), dim3(grids[ST_JOIN]), dim3(NT3), 0, st, J, M, sorted);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((k_join<false, MULTI>), dim3(grids[ST_JOIN]), dim3(NT3), 0, st, J, M, (uint64_t *)nullptr);
+    rec(5);
+    hipLaunchKernelGGL((k_recover_few<MULTI>), dim3(grids[ST_RFEW], 2), dim3(NT1), 0, st, J, M);
+    hipLaunchKernelGGL((k_recover<MULTI>), dim3(grids[ST_RMANY], 2), dim3(NT1), 0, st, J, M);
+    hipLaunchKernelGGL((k_pairs<MULTI>), dim3(grids[ST_PAIRS]), dim3(NT1), 0, st, J, M);
+    rec(6);
     return hipGetLastError();
 }
 
@@ -924,38 +1030,27 @@ rfr_status enqueue_recombine(const uint64_t *w, int n, uint64_t t_lo, uint64_t t
         err = "rfr_recombine_dev: window must satisfy t_lo + t_hi < 2^32";
         return RFR_EINVAL;
     }
+    if (cap < 1) {
+        err = "rfr_recombine_dev: cap must be at least 1";
+        return RFR_EINVAL;
+    }
     int na, nb;
     split_halves(n, na, nb);
     JobPlan P;
-    uint64_t need = plan_job(na, nb, P);
+    uint64_t need = plan_job(na, nb, P, KCAP_MAX);
     if (ws_bytes < need) {
         err = "rfr_recombine_dev: workspace too small";
         return RFR_ENOMEM;
     }
-    JobArgs J;
     std::vector<uint64_t> wneg(nb);
     for (int i = 0; i < nb; ++i) wneg[i] = 0 - w[na + i];
-    enqueue_common(P, (char *)ws, w, wneg.data(), J);
-    J.t_lo = t_lo;
-    J.t_hi = t_hi;
+    JobArgs J;
+    build_job(P, (char *)ws, w, wneg.data(), t_lo, t_hi, cand, count, cap, J);
     J.kcap = std::min<uint64_t>(cap + 1, KCAP_MAX);
-    J.out = cand;
-    J.out_count = count;
-    J.cap = cap;
-    if (launch_front(P, J, st, ev) != hipSuccess) {
-        err = "kernel launch failed";
-        return RFR_EDEVICE;
-    }
-    hipLaunchKernelGGL(k_join<false>, dim3(1u << (P.B1 + P.B2)), dim3(NT3), 0, st, J, (uint64_t *)nullptr);
-    if (ev && ev->ev[5]) (void)hipEventRecord((hipEvent_t)ev->ev[5], st);
-    uint32_t mw = std::max(P.h[0].nwg1, P.h[1].nwg1);
-    const uint64_t msteps = std::max(P.h[0].steps, P.h[1].steps);
-    const uint32_t g4 = (uint32_t)((msteps + (uint64_t)NT1 * SPT4 - 1) / ((uint64_t)NT1 * SPT4));
-    hipLaunchKernelGGL(k_recover_few, dim3(g4, 2), dim3(NT1), 0, st, J);
-    hipLaunchKernelGGL(k_recover, dim3(mw, 2), dim3(NT1), 0, st, J);
-    hipLaunchKernelGGL(k_pairs, dim3(1), dim3(NT1), 0, st, J);
-    if (ev && ev->ev[6]) (void)hipEventRecord((hipEvent_t)ev->ev[6], st);
-    if (hipGetLastError() != hipSuccess) {
+    uint32_t grids[NSTAGES];
+    stage_blocks(P, grids);
+    Multi M{nullptr, nullptr, 0};
+    if (launch_all<false>(J, M, grids, 2, P.B1, P.B2, true, nullptr, st, ev) != hipSuccess) {
         err = "kernel launch failed";
         return RFR_EDEVICE;
     }
@@ -967,13 +1062,13 @@ size_t recombine_workspace(int n) {
     int na, nb;
     split_halves(n, na, nb);
     JobPlan P;
-    return plan_job(na, nb, P);
+    return plan_job(na, nb, P, KCAP_MAX);
 }
 
 size_t expand_workspace(int m) {
     if (m < 1 || m > 30) return 0;
     JobPlan P;
-    return plan_job(m, -1, P);
+    return plan_job(m, -1, P, 1);
 }
 
 rfr_status enqueue_expand(const uint64_t *w, int m, int negate, void *ws, size_t ws_bytes,
@@ -983,7 +1078,7 @@ rfr_status enqueue_expand(const uint64_t *w, int m, int negate, void *ws, size_t
         return RFR_EINVAL;
     }
     JobPlan P;
-    uint64_t need = plan_job(m, -1, P);
+    uint64_t need = plan_job(m, -1, P, 1);
     if (ws_bytes < need) {
         err = "rfr_expand_dev: workspace too small";
         return RFR_ENOMEM;
@@ -992,18 +1087,159 @@ rfr_status enqueue_expand(const uint64_t *w, int m, int negate, void *ws, size_t
     if (negate)
         for (auto &v : ww) v = 0 - v;
     JobArgs J;
-    enqueue_common(P, (char *)ws, ww.data(), nullptr, J);
+    build_job(P, (char *)ws, ww.data(), nullptr, 0, 0, nullptr, nullptr, 0, J);
     J.kcap = 1;
-    if (launch_front(P, J, st, nullptr) != hipSuccess) {
-        err = "kernel launch failed";
-        return RFR_EDEVICE;
-    }
-    hipLaunchKernelGGL(k_join<true>, dim3(1u << (P.B1 + P.B2)), dim3(NT3), 0, st, J, sorted);
-    if (hipGetLastError() != hipSuccess) {
+    uint32_t grids[NSTAGES];
+    stage_blocks(P, grids);
+    Multi M{nullptr, nullptr, 0};
+    if (launch_all<false>(J, M, grids, 1, P.B1, P.B2, false, sorted, st, nullptr) != hipSuccess) {
         err = "kernel launch failed";
         return RFR_EDEVICE;
     }
     return RFR_OK;
+}
+
+// ---------------------------------------------------------------- batches
+void MultiLaunch::add(const JobPlan &P, const JobArgs &J) {
+    uint32_t x[NSTAGES];
+    stage_blocks(P, x);
+    if (bases.empty()) bases.assign(NSTAGES, std::vector<uint32_t>(1, 0));
+    for (int s = 0; s < NSTAGES; ++s) bases[s].push_back(bases[s].back() + x[s]);
+    jobs.push_back(J);
+    maxB1 = std::max(maxB1, P.B1);
+    maxB2 = std::max(maxB2, P.B2);
+}
+
+size_t MultiLaunch::bases_bytes() const { return (size_t)NSTAGES * (jobs.size() + 1) * 4; }
+
+void MultiLaunch::pack_bases(uint32_t *dst) const {
+    const size_t nj = jobs.size();
+    for (int s = 0; s < NSTAGES; ++s)
+        for (size_t j = 0; j <= nj; ++j) dst[s * (nj + 1) + j] = bases.empty() ? 0 : bases[s][j];
+}
+
+hipError_t MultiLaunch::launch(const JobArgs *jobs_dev, const uint32_t *bases_dev, hipStream_t st,
+                               StageEvents *ev) const {
+    if (jobs.empty()) return hipSuccess;
+    Multi M{jobs_dev, bases_dev, (int)jobs.size()};
+    uint32_t grids[NSTAGES];
+    for (int s = 0; s < NSTAGES; ++s) grids[s] = bases[s].back();
+    JobArgs dummy{};
+    return launch_all<true>(dummy, M, grids, 2, maxB1, maxB2, true, nullptr, st, ev);
+}
+
+// ---------------------------------------------------------------- small searches
+// One workgroup searches one polynomial with both halves <= 2^SMALL_HALF keys
+// entirely in LDS: A's sums by pattern index, B' radix-sorted by its top LB3
+// bits together with its pattern index, then every a probes the bins its
+// cyclic window overlaps and emits pattern pairs directly.  Workgroups are
+// persistent and take the next job (largest first) from an atomic counter.
+__global__ __launch_bounds__(NT3) void k_small(const SmallJob *jobs, int njobs, uint32_t *queue) {
+    __shared__ uint64_t s_a[1 << SMALL_HALF];
+    __shared__ uint64_t s_b[1 << SMALL_HALF];
+    __shared__ uint16_t s_bi[1 << SMALL_HALF];
+    __shared__ uint32_t s_bin[NB3 + 1];
+    __shared__ uint64_t s_tmp[NT3 / 64 + 2];
+    __shared__ int s_job;
+    __shared__ unsigned long long s_cnt;
+    const int tid = threadIdx.x;
+    constexpr int KPS = (1 << SMALL_HALF) / NT3;
+    for (;;) {
+        if (tid == 0) s_job = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int j = s_job;
+        if (j >= njobs) return;
+        const SmallJob &S = jobs[j];
+        const int na = S.na, nb = S.nb;
+        const uint32_t NA = 1u << na, NBk = 1u << nb;
+        for (int i = tid; i < NB3; i += NT3) s_bin[i] = 0;
+        if (tid == 0) s_cnt = 0;
+        for (uint32_t i = tid; i < NA; i += NT3) {
+            uint64_t v = 0;
+            for (int e = 0; e < na; ++e)
+                if ((i >> e) & 1) v += S.w[e];
+            s_a[i] = v;
+        }
+        __syncthreads();
+        uint64_t kb[KPS];
+        uint32_t rk[KPS];
+#pragma unroll
+        for (int k = 0; k < KPS; ++k) {
+            const uint32_t i = tid + k * NT3;
+            if (i < NBk) {
+                uint64_t v = 0;
+                for (int e = 0; e < nb; ++e)
+                    if ((i >> e) & 1) v -= S.w[na + e];
+                kb[k] = v;
+                rk[k] = atomicAdd(&s_bin[(uint32_t)(v >> (64 - LB3))], 1u);
+            }
+        }
+        __syncthreads();
+        lds_excl_scan<NT3, NB3 / NT3>(s_bin, NB3, s_tmp);
+        if (tid == 0) s_bin[NB3] = NBk;
+#pragma unroll
+        for (int k = 0; k < KPS; ++k) {
+            const uint32_t i = tid + k * NT3;
+            if (i < NBk) {
+                const uint32_t p = s_bin[(uint32_t)(kb[k] >> (64 - LB3))] + rk[k];
+                s_b[p] = kb[k];
+                s_bi[p] = (uint16_t)i;
+            }
+        }
+        __syncthreads();
+        const uint64_t t_lo = S.t_lo, t_hi = S.t_hi;
+        for (uint32_t i = tid; i < NA; i += NT3) {
+            const uint64_t a = s_a[i];
+            // the cyclic window [a - t_hi, a + t_lo] as up to two plain ranges
+            uint64_t lo[2], hi[2];
+            int nr = 0;
+            if (a >= t_hi) {
+                lo[0] = a - t_hi;
+            } else {
+                lo[0] = 0;
+                lo[1] = a - t_hi;  // wraps: [2^64 - (t_hi - a), 2^64)
+                hi[1] = ~0ull;
+                nr = 1;
+            }
+            if (a <= ~0ull - t_lo) {
+                hi[0] = a + t_lo;
+            } else {
+                hi[0] = ~0ull;
+                lo[1] = 0;
+                hi[1] = a + t_lo;  // wraps: [0, a + t_lo - 2^64]
+                nr = 1;
+            }
+            for (int r = 0; r <= nr; ++r) {
+                const uint32_t b0 = (uint32_t)(lo[r] >> (64 - LB3)), b1 = (uint32_t)(hi[r] >> (64 - LB3));
+                const uint32_t e = s_bin[b1 + 1];
+                for (uint32_t q = s_bin[b0]; q < e; ++q) {
+                    const uint64_t bk = s_b[q];
+                    if (bk < lo[r] || bk > hi[r]) continue;
+                    const uint32_t pb = s_bi[q];
+                    if (i == 0 && pb == 0) continue;  // the empty pattern
+                    const unsigned long long o = atomicAdd(&s_cnt, 1ull);
+                    if (o < S.cap) {
+                        S.out[2 * o] = i;
+                        S.out[2 * o + 1] = pb;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (tid == 0) *S.out_count = s_cnt > S.cap ? ~0ull : s_cnt;
+        __syncthreads();
+    }
+}
+
+__global__ void k_small_init(uint32_t *queue) {
+    if (threadIdx.x == 0) *queue = 0;
+}
+
+hipError_t launch_small(const SmallJob *jobs_dev, int njobs, uint32_t *queue_dev, int grid, hipStream_t st) {
+    if (njobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_small_init, dim3(1), dim3(64), 0, st, queue_dev);
+    hipLaunchKernelGGL(k_small, dim3(grid), dim3(NT3), 0, st, jobs_dev, njobs, queue_dev);
+    return hipGetLastError();
 }
 
 }  // namespace rfr

@@ -258,66 +258,111 @@ static void aberth(const std::vector<double> &a, std::vector<cplx> &z, int maxit
     }
 }
 
-// Complex double-double Horner: p(z), p'(z) and a bound on the rounding error
-// of p(z) (and of p'(z)).
-struct Eval {
-    cdd p, dp;
-    double err_p, err_dp;
+// Newton data at z in complex double-double: the step p(z)/p'(z) and the
+// inclusion radius d |p(z)| / |p'(z)| (a root lies within it), bounded with
+// the rounding error of the evaluation.  For |z| > 1 the polynomial is
+// evaluated reversed at y = 1/z (p(z) = z^d q(y), p'(z) = z^(d-1) (d q - y q'))
+// so no intermediate overflows for large roots.
+struct Newton {
+    cdd step;
+    double radius;
 };
-static Eval eval_cdd(const std::vector<dd> &a, const cdd &z) {
-    int d = (int)a.size() - 1;
-    cdd p{a[d], mkdd(0)}, dp{mkdd(0), mkdd(0)};
-    double az = cabs_d(z), s = std::fabs(to_d(a[d])), ds = 0;
-    for (int i = d - 1; i >= 0; --i) {
-        dp = dp * z + p;
-        p = p * z + cdd{a[i], mkdd(0)};
-        ds = ds * az + s;
-        s = s * az + std::fabs(to_d(a[i]));
+static const double kHornerU = 16.0 * 5.0e-32;  // > 16 * 2^-104 (complex dd mul-add)
+
+static Newton newton_c(const std::vector<dd> &a, const cdd &z) {
+    const int d = (int)a.size() - 1;
+    const double az = cabs_d(z);
+    Newton out;
+    if (az <= 1.0) {
+        cdd p{a[d], mkdd(0)}, dp{mkdd(0), mkdd(0)};
+        double s = std::fabs(to_d(a[d])), ds = 0;
+        for (int i = d - 1; i >= 0; --i) {
+            dp = dp * z + p;
+            p = p * z + cdd{a[i], mkdd(0)};
+            ds = ds * az + s;
+            s = s * az + std::fabs(to_d(a[i]));
+        }
+        const double ep = 2.0 * d * kHornerU * s, edp = 2.0 * d * kHornerU * ds;
+        const double adp = cabs_d(dp) - edp;
+        out.step = cabs_d(dp) > 0 ? p / dp : cdd{mkdd(0), mkdd(0)};
+        out.radius = adp > 0 ? d * (cabs_d(p) + ep) / adp * (1 + 1e-12) : INFINITY;
+        return out;
     }
-    // each complex dd multiply-add has relative error below ~16 * 2^-104;
-    // Horner accumulates at most 2d of them
-    const double u = 16.0 * std::ldexp(1.0, -104);
-    return {p, dp, 2.0 * d * u * s * 1.01, 2.0 * d * u * ds * 1.01};
-}
-static Eval eval_rdd(const std::vector<dd> &a, const dd &x) {
-    int d = (int)a.size() - 1;
-    dd p = a[d], dp = mkdd(0);
-    double ax = std::fabs(to_d(x)), s = std::fabs(to_d(a[d])), ds = 0;
-    for (int i = d - 1; i >= 0; --i) {
-        dp = dp * x + p;
-        p = p * x + a[i];
-        ds = ds * ax + s;
-        s = s * ax + std::fabs(to_d(a[i]));
+    const cdd one{mkdd(1), mkdd(0)};
+    const cdd y = one / z;
+    const double ay = cabs_d(y);
+    cdd q{a[0], mkdd(0)}, dq{mkdd(0), mkdd(0)};
+    double s = std::fabs(to_d(a[0])), ds = 0;
+    for (int i = 1; i <= d; ++i) {
+        dq = dq * y + q;
+        q = q * y + cdd{a[i], mkdd(0)};
+        ds = ds * ay + s;
+        s = s * ay + std::fabs(to_d(a[i]));
     }
-    const double u = 8.0 * std::ldexp(1.0, -104);
-    return {{p, mkdd(0)}, {dp, mkdd(0)}, 2.0 * d * u * s * 1.01, 2.0 * d * u * ds * 1.01};
+    const double eq = 2.0 * d * kHornerU * s, edq = 2.0 * d * kHornerU * ds;
+    const cdd den = cdd{q.re * (double)d, q.im * (double)d} - y * dq;
+    const double aden = cabs_d(den) - d * eq - ay * edq;
+    out.step = cabs_d(den) > 0 ? (z * q) / den : cdd{mkdd(0), mkdd(0)};
+    out.radius = aden > 0 ? d * az * (cabs_d(q) + eq) / aden * (1 + 1e-12) : INFINITY;
+    return out;
 }
 
-// Newton inclusion radius: a root lies within d |p(z)| / |p'(z)|.
-static double radius_of(const Eval &e, int d) {
-    double ap = cabs_d(e.p) + e.err_p;
-    double adp = cabs_d(e.dp) - e.err_dp;
-    if (!(adp > 0)) return INFINITY;
-    return d * ap / adp * (1.0 + 1e-12);
+// The same on the real axis (real double-double arithmetic).
+struct NewtonR {
+    dd step;
+    double radius;
+};
+static NewtonR newton_r(const std::vector<dd> &a, const dd &x) {
+    const int d = (int)a.size() - 1;
+    const double ax = std::fabs(to_d(x));
+    const double u = 8.0 * 5.0e-32;
+    NewtonR out;
+    if (ax <= 1.0) {
+        dd p = a[d], dp = mkdd(0);
+        double s = std::fabs(to_d(a[d])), ds = 0;
+        for (int i = d - 1; i >= 0; --i) {
+            dp = dp * x + p;
+            p = p * x + a[i];
+            ds = ds * ax + s;
+            s = s * ax + std::fabs(to_d(a[i]));
+        }
+        const double ep = 2.0 * d * u * s, edp = 2.0 * d * u * ds;
+        const double adp = std::fabs(to_d(dp)) - edp;
+        out.step = to_d(dp) != 0 ? p / dp : mkdd(0);
+        out.radius = adp > 0 ? d * (std::fabs(to_d(p)) + ep) / adp * (1 + 1e-12) : INFINITY;
+        return out;
+    }
+    const dd y = mkdd(1) / x;
+    const double ay = std::fabs(to_d(y));
+    dd q = a[0], dq = mkdd(0);
+    double s = std::fabs(to_d(a[0])), ds = 0;
+    for (int i = 1; i <= d; ++i) {
+        dq = dq * y + q;
+        q = q * y + a[i];
+        ds = ds * ay + s;
+        s = s * ay + std::fabs(to_d(a[i]));
+    }
+    const double eq = 2.0 * d * u * s, edq = 2.0 * d * u * ds;
+    const dd den = q * (double)d - y * dq;
+    const double aden = std::fabs(to_d(den)) - d * eq - ay * edq;
+    out.step = to_d(den) != 0 ? (x * q) / den : mkdd(0);
+    out.radius = aden > 0 ? d * ax * (std::fabs(to_d(q)) + eq) / aden * (1 + 1e-12) : INFINITY;
+    return out;
 }
 
 static cdd polish_c(const std::vector<dd> &a, cdd z, int iters) {
     for (int k = 0; k < iters; ++k) {
-        Eval e = eval_cdd(a, z);
-        if (cabs_d(e.dp) == 0) break;
-        cdd step = e.p / e.dp;
-        z = z - step;
-        if (cabs_d(step) <= 1e-31 * std::max(cabs_d(z), 1e-300)) break;
+        const Newton nw = newton_c(a, z);
+        z = z - nw.step;
+        if (cabs_d(nw.step) <= 1e-31 * std::max(cabs_d(z), 1e-300)) break;
     }
     return z;
 }
 static dd polish_r(const std::vector<dd> &a, dd x, int iters) {
     for (int k = 0; k < iters; ++k) {
-        Eval e = eval_rdd(a, x);
-        if (to_d(e.dp.re) == 0) break;
-        dd step = e.p.re / e.dp.re;
-        x = x - step;
-        if (std::fabs(to_d(step)) <= 1e-31 * std::max(std::fabs(to_d(x)), 1e-300)) break;
+        const NewtonR nw = newton_r(a, x);
+        x = x - nw.step;
+        if (std::fabs(to_d(nw.step)) <= 1e-31 * std::max(std::fabs(to_d(x)), 1e-300)) break;
     }
     return x;
 }
@@ -327,6 +372,8 @@ struct Disc {
     double r;
 };
 static bool discs_disjoint(const std::vector<Disc> &D) {
+    for (auto &x : D)
+        if (!std::isfinite(x.c.real()) || !std::isfinite(x.c.imag()) || !std::isfinite(x.r)) return false;
     // sort by real part and sweep
     std::vector<int> o(D.size());
     std::iota(o.begin(), o.end(), 0);
@@ -362,9 +409,11 @@ static void fail_roots(const Prepared &P, rfr_status &st, std::string &err, cons
 
 // floor(frac(v) * 2^64) mod 2^64 for a double-double v, |v| < 2^60.
 static uint64_t weight_of(dd v) {
-    double fl = std::floor(v.hi);
-    dd f = two_sum(v.hi - fl, v.lo);  // v.hi - fl is exact
-    f = quick_two_sum(f.hi, f.lo);
+    // v - floor(v.hi) as an exact double-double: v.hi - fl is not exactly
+    // representable when v.hi lies in (-0.5, 0), so it goes through two_sum
+    const double fl = std::floor(v.hi);
+    dd f = two_sum(v.hi, -fl);
+    f = f + mkdd(v.lo);
     while (f.hi < 0) f = f + mkdd(1.0);
     while (f.hi >= 1.0) f = f - mkdd(1.0);
     // f in [0,1) as hi + lo; scale by 2^64 exactly
@@ -404,9 +453,8 @@ rfr_status prepare_elements(Prepared &P, std::string &err) {
     for (int i = 0; i < d; ++i) {
         cdd c{mkdd(z[i].real()), mkdd(z[i].imag())};
         c = polish_c(add, c, 6);
-        Eval e = eval_cdd(add, c);
         zc[i] = c;
-        D[i] = {cplx(to_d(c.re), to_d(c.im)), radius_of(e, d)};
+        D[i] = {cplx(to_d(c.re), to_d(c.im)), newton_c(add, c).radius};
     }
     rfr_status st = RFR_OK;
     if (!discs_disjoint(D)) {
@@ -422,8 +470,7 @@ rfr_status prepare_elements(Prepared &P, std::string &err) {
     for (int i = 0; i < d; ++i) {
         if (std::fabs(D[i].c.imag()) <= D[i].r) {
             dd x = polish_r(add, zc[i].re, 6);
-            Eval e = eval_rdd(add, x);
-            double rx = radius_of(e, d);
+            double rx = newton_r(add, x).radius;
             reals.push_back(x);
             rr.push_back(rx);
             F.push_back({cplx(to_d(x), 0), rx});

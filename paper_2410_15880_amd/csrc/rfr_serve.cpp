@@ -70,6 +70,13 @@ static Slot *acquire_slot(rfr_ctx *ctx, size_t need, rfr_status &st) {
             st = RFR_OK;
             return best;
         }
+        bool any_busy = false;
+        for (auto &s : ctx->slots) any_busy = any_busy || s.busy;
+        if (!any_busy) {
+            // nothing running will free memory: this request cannot be admitted
+            st = fail(RFR_ENOMEM, "request tables do not fit the free memory budget");
+            return nullptr;
+        }
         ctx->cv_slot.wait(lk);
     }
 }
@@ -152,6 +159,14 @@ rfr_status rfr_serve_start(rfr_ctx *ctx, int max_active, int host_threads) {
         return fail(RFR_EINVAL, "max_active in [1,64], host_threads in [1,256]");
     if (ctx->serving) return fail(RFR_EBUSY, "already serving");
     (void)hipSetDevice(ctx->device);
+    // the serving slots trade workspaces among themselves: hand back the plain
+    // path's workspace so its memory is available to admission
+    if (ctx->main.ws) {
+        (void)hipFree(ctx->main.ws);
+        ctx->mem_used -= ctx->main.ws_bytes;
+        ctx->main.ws = nullptr;
+        ctx->main.ws_bytes = 0;
+    }
     ctx->slots.assign(max_active, Slot());
     for (auto &s : ctx->slots) {
         rfr_status st = slot_init(ctx, s);

@@ -1,0 +1,167 @@
+"""CPU tests of the library's host side (no GPU needed).
+
+* every symbol include/rfr.h declares is exported by librfr.so;
+* the host-stage weights and window (rfr_weights) agree with the oracle's
+  high-precision values: identical, or within the window's own error bound;
+* error paths of the host stages;
+* the window is conservative: planted factors' residues lie inside it.
+"""
+import os
+import re
+import subprocess
+
+import pytest
+
+from oracle import rfr_ref as O
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+MOD = 1 << 64
+
+
+@pytest.fixture(scope="module")
+def R():
+    import paper_2410_15880_amd as R
+    R.lib()
+    return R
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "rfr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(rfr_[a-z_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol(R):
+    decl = declared_symbols()
+    assert len(decl) >= 15
+    out = subprocess.run(["nm", "-D", "--defined-only", R.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(line.split()[-1] for line in out.splitlines() if line.strip())
+    missing = [d for d in decl if d not in exported]
+    assert not missing, missing
+    assert sorted(decl) == sorted(R.EXPORTS)
+
+
+def _signed(x):
+    return ((x + (1 << 63)) % MOD) - (1 << 63)
+
+
+@pytest.mark.parametrize("coeffs", [[6, -5, 1], [-2, 0, 1], [-1, 0, 2], [5, 3, 7], [1, 0, -10, 0, 1],
+                                    [3, 7], [-1, 0, 0, 0, 0, 0, 1]])
+def test_weights_match_oracle_small(R, coeffs):
+    got = R.weights(coeffs)
+    tr = O.Trace()
+    O.factor(coeffs, tr)
+    assert got["n"] == tr.n
+    # same elements in the same canonical order; weights within the window
+    for a, b in zip(got["w"], tr.w):
+        assert abs(_signed(a - b)) <= got["t_hi"]
+
+
+def test_weights_match_oracle_configs(R):
+    for w in [W.config_small()] + W.config_mid()[::3] + W.config_batch()[:40:5]:
+        got = R.weights(w.coeffs)
+        cont, k, prim = O.normalise(w.coeffs)
+        ts, groups, deltas = O.elements(prim)
+        ow = O.weights(prim, ts)
+        assert got["n"] == len(ts)
+        assert got["r"] == sum(1 for g in groups if g[0] == "r")
+        for a, b in zip(got["w"], ow):
+            assert abs(_signed(a - b)) <= got["t_hi"], w.seed
+        # the window accounts for floor quantisation of n weights
+        assert got["t_lo"] >= got["n"] + got["t_hi"]
+
+
+def test_window_conservative_on_planted(R):
+    # each planted factor's subset of the product's weights sums into the window
+    for w in W.config_mid()[8:]:
+        got = R.weights(w.coeffs)
+        tr = O.Trace()
+        O.factor(w.coeffs, tr)
+        for s in tr.confirmed:
+            tot = sum(got["w"][i] for i in range(got["n"]) if (s >> i) & 1)
+            assert O.in_window(tot, got["t_lo"], got["t_hi"])
+
+
+def test_weights_errors(R):
+    with pytest.raises(R.RFRError) as e:
+        R.weights([1, -2, 1])
+    assert e.value.name == "RFR_ENOTSQFREE"
+    with pytest.raises(R.RFRError) as e:
+        R.weights([0, 0, 3])
+    assert e.value.name == "RFR_ENOTSQFREE"
+    with pytest.raises(R.RFRError) as e:
+        R.weights([4])
+    assert e.value.name == "RFR_EINVAL"
+    with pytest.raises(R.RFRError) as e:
+        R.weights([1, 2, 0])
+    assert e.value.name == "RFR_EINVAL"
+
+
+def test_workspace_sizes(R):
+    L = R.lib()
+    assert L.rfr_recombine_workspace_bytes(1) == 0
+    assert L.rfr_recombine_workspace_bytes(200) == 0
+    prev = 0
+    for n in range(2, 60):
+        b = L.rfr_recombine_workspace_bytes(n)
+        na = (n - 1 + 1) // 2
+        nb = (n - 1) // 2
+        assert b >= 8 * ((1 << na) + (1 << nb))
+        assert b >= prev
+        prev = b
+    assert L.rfr_expand_workspace_bytes(0) == 0
+    assert L.rfr_expand_workspace_bytes(20) >= 8 << 20
+
+
+def test_kernel_entry_rejects_bad_arguments_on_host(R):
+    # argument checks happen before anything touches a device
+    import ctypes as C
+    L = R.lib()
+    w = (C.c_uint64 * 4)(1, 2, 3, 4)
+    st = L.rfr_recombine_dev(w, 1, 0, 0, None, 0, None, None, 1, None)
+    assert st == -1
+    st = L.rfr_recombine_dev(w, 4, 1 << 33, 0, C.c_void_p(1), 1 << 20, None, C.c_void_p(1), 1, C.c_void_p(1))
+    assert st == -1
+    st = L.rfr_expand_dev(w, 0, 0, None, 0, None, None)
+    assert st == -1
+
+
+def test_large_roots_do_not_overflow(R):
+    # degree-62 and degree-90 inputs with roots near -340 and +100: the Newton
+    # step of the polish must not overflow (|p'|^2 > 1e308 if evaluated directly)
+    reqs = W.config_stream(300, rate_per_s=1.0, dcap=110)
+    for k in (74, 264):
+        c = reqs[k].work.coeffs
+        got = R.weights(c)
+        cont, kk, prim = O.normalise(c)
+        ts, groups, deltas = O.elements(prim)
+        assert got["n"] == len(ts)
+        ow = O.weights(prim, ts)
+        for a, b in zip(got["w"], ow):
+            assert abs(_signed(a - b)) <= got["t_hi"]
+
+
+def test_every_stream_request_prepares(R):
+    # host roots succeed on the served workload's degree range (up to 128)
+    for r in W.config_stream(400, rate_per_s=1.0):
+        R.weights(r.work.coeffs)
+
+
+def test_weights_rounding_tight_against_oracle(R):
+    # the product's double-double weights agree with the oracle's 400-bit
+    # weights to within a few units (the window only has to cover root error
+    # and the floor); this catches any lost bit in the fractional part
+    rng = __import__("random").Random(17)
+    sample = [w.coeffs for w in rng.sample(W.config_batch(), 24)]
+    sample += [r.work.coeffs for r in W.config_stream(60, rate_per_s=1.0)[::6]]
+    worst = 0
+    for c in sample:
+        got = R.weights(c)
+        cont, kk, prim = O.normalise(c)
+        ts, groups, deltas = O.elements(prim)
+        ow = O.weights(prim, ts)
+        for a, b in zip(got["w"], ow):
+            worst = max(worst, abs(_signed(a - b)))
+    assert worst <= 4, worst
