@@ -156,6 +156,20 @@ typedef struct rfr_profile_t {
 rfr_status rfr_profile(rfr_ctx *ctx, int enable);
 rfr_status rfr_profile_read(rfr_ctx *ctx, rfr_profile_t *out);
 
+/* ------------------------------------------------------------------ tuning */
+
+/* Time the device search for every radix split candidate of each size class
+ * lg in [lg_lo, lg_hi] (halves of 2^lg keys; 8 <= lg_lo <= lg_hi <= 28): the
+ * sub-bucket size (2^10 or 2^11 keys) and the level-1 digit bits.  Installs
+ * the fastest split per class for this process and, if path_out is not NULL,
+ * writes the table ("lg b1 sub_log ms" lines).  Not concurrent with other
+ * calls.  Contexts load RFR_TUNING or the package's tuning/mi355x.txt at
+ * creation. */
+rfr_status rfr_autotune(rfr_ctx *ctx, int lg_lo, int lg_hi, const char *path_out);
+
+/* Install a table written by rfr_autotune. */
+rfr_status rfr_load_tuning(const char *path);
+
 /* ------------------------------------------------------------------ results */
 
 void rfr_result_free(rfr_result *res);
@@ -174,15 +188,23 @@ rfr_status rfr_weights(const int64_t *coeffs, int degree, uint64_t *w_out, int32
 
 /* ------------------------------------------------------------------ kernel level */
 
-/* Device workspace needed by rfr_recombine_dev for n elements. */
+/* Device workspace for rfr_recombine_dev to search n elements in one pass. */
 size_t rfr_recombine_workspace_bytes(int n);
+
+/* Smallest workspace rfr_recombine_dev accepts for n elements.  Between this
+ * and rfr_recombine_workspace_bytes(n) the search streams half A in chunks:
+ * half B' is built and sorted once and stays resident, and half A is
+ * enumerated, sorted and joined 2^c times with its top c weights fixed per
+ * chunk (c the smallest that fits, at most 8). */
+size_t rfr_recombine_min_workspace_bytes(int n);
 
 /*
  * The recombination search (Section 3.3, Algorithm C with a FIND that reports
  * every pair): all patterns s in [1, 2^(n-1)) over the first n-1 weights whose
  * sum mod 2^64 lies in [2^64 - t_lo, 2^64) U [0, t_hi].
  *   w_host     host array of n weights (borrowed for the call)
- *   workspace  device buffer of at least rfr_recombine_workspace_bytes(n)
+ *   workspace  device buffer of ws_bytes >= rfr_recombine_min_workspace_bytes(n)
+ *              (less than rfr_recombine_workspace_bytes(n) streams half A)
  *   hip_stream hipStream_t the work is queued on (NULL = default stream)
  *   cand_dev   device array of 2*cap uint64: pattern k is split as
  *              cand_dev[2k] = bits of elements [0, n_a) and

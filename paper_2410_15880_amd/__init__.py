@@ -27,7 +27,8 @@ EXPORTS = [
     "rfr_serve_start", "rfr_submit", "rfr_poll", "rfr_serve_stop", "rfr_result_free",
     "rfr_strerror", "rfr_last_error", "rfr_weights", "rfr_recombine_workspace_bytes",
     "rfr_recombine_dev", "rfr_expand_workspace_bytes", "rfr_expand_dev",
-    "rfr_profile", "rfr_profile_read",
+    "rfr_profile", "rfr_profile_read", "rfr_recombine_min_workspace_bytes",
+    "rfr_autotune", "rfr_load_tuning",
 ]
 
 
@@ -87,10 +88,13 @@ def lib():
         "rfr_weights": ([C.POINTER(i64), C.c_int, C.POINTER(u64), C.POINTER(i32), C.POINTER(i32),
                          C.POINTER(u64), C.POINTER(u64)], C.c_int),
         "rfr_recombine_workspace_bytes": ([C.c_int], sz),
+        "rfr_recombine_min_workspace_bytes": ([C.c_int], sz),
         "rfr_recombine_dev": ([C.POINTER(u64), C.c_int, u64, u64, P, sz, P, P, u64, P], C.c_int),
         "rfr_expand_workspace_bytes": ([C.c_int], sz),
         "rfr_expand_dev": ([C.POINTER(u64), C.c_int, C.c_int, P, sz, P, P], C.c_int),
         "rfr_profile": ([P, C.c_int], C.c_int),
+        "rfr_autotune": ([P, C.c_int, C.c_int, C.c_char_p], C.c_int),
+        "rfr_load_tuning": ([C.c_char_p], C.c_int),
         "rfr_profile_read": ([P, C.POINTER(Profile)], C.c_int),
     }
     for name, (args, res) in sig.items():
@@ -124,6 +128,13 @@ def _unpack(rp) -> dict:
            "ms_search": r.ms_search, "ms_confirm": r.ms_confirm}
     lib().rfr_result_free(rp)
     return out
+
+
+TUNING_PATH = os.path.join(_PKG, "tuning", "mi355x.txt")
+
+
+def load_tuning(path: str = TUNING_PATH):
+    _check(lib().rfr_load_tuning(path.encode()))
 
 
 def weights(coeffs: Sequence[int]) -> dict:
@@ -189,6 +200,11 @@ class Context:
                 res.append(RFRError(sts[i], "batch entry %d" % i))
         return res
 
+    # ---- tuning
+    def autotune(self, lg_lo: int = 12, lg_hi: int = 27, path: Optional[str] = None):
+        """Time every radix split per size class on this device; install the best."""
+        _check(lib().rfr_autotune(self._h, lg_lo, lg_hi, path.encode() if path else None))
+
     # ---- profiling
     def profile(self, enable: bool = True):
         _check(lib().rfr_profile(self._h, 1 if enable else 0))
@@ -234,7 +250,7 @@ def _stream_ptr(stream=None):
 
 
 def recombine_dev(w: Sequence[int], t_lo: int, t_hi: int, cap: int = 4096, stream=None,
-                  workspace=None, sync: bool = True):
+                  workspace=None, sync: bool = True, ws_bytes: Optional[int] = None):
     """Search on the device over caller-owned torch buffers.
 
     Returns the list of patterns s (ints, bit i = element i of the first n-1),
@@ -244,7 +260,8 @@ def recombine_dev(w: Sequence[int], t_lo: int, t_hi: int, cap: int = 4096, strea
     import torch
     n = len(w)
     L = lib()
-    ws_bytes = L.rfr_recombine_workspace_bytes(n)
+    if ws_bytes is None:
+        ws_bytes = L.rfr_recombine_workspace_bytes(n)
     if workspace is None:
         workspace = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device="cuda")
     cand = torch.empty(2 * cap, dtype=torch.int64, device="cuda")

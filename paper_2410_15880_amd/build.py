@@ -39,6 +39,7 @@ UNITS = [
     ("rfr_abi.cpp", "hiphost"),
     ("rfr_batch.cpp", "hip"),
     ("rfr_serve.cpp", "hiphost"),
+    ("rfr_tune.cpp", "hiphost"),
 ]
 
 
@@ -75,7 +76,7 @@ def build(verbose: bool = False) -> str:
         msg = "\n".join("--- %s ---\n%s" % f for f in failed)
         raise RuntimeError("librfr build failed:\n" + msg)
     tmp = LIB + ".tmp"
-    link = [HIPCC, "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
+    link = [HIPCC, "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread", "-ldl"]
     if verbose:
         print(" ".join(link), flush=True)
     r = subprocess.run(link, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)

@@ -94,13 +94,35 @@ void slot_free(rfr_ctx *ctx, Slot &s) {
 }
 
 // Device search for a prepared polynomial on one slot; fills cands.
+// Workspace for a search over n weights within `avail` bytes: the full tables
+// if they fit, else the smallest chunked layout (half A streamed in chunks)
+// that does; 0 if none fits.
+size_t choose_workspace(int n, size_t avail) {
+    size_t full = recombine_workspace(n);
+    if (full <= avail) return full;
+    int na, nb;
+    split_halves(n, na, nb);
+    for (int c = 1; c <= std::min(na, dev::MAX_CHUNK_BITS); ++c) {
+        JobPlan P;
+        size_t b = plan_job(na - c, nb, P, dev::KCAP_MAX);
+        if (b <= avail) return b;
+    }
+    return 0;
+}
+
 rfr_status search_on_slot(rfr_ctx *ctx, Slot &s, const Prepared &P, std::vector<Pat> &cands) {
     cands.clear();
     if (P.n <= 1) return RFR_OK;
     if (P.n > 2 * dev::MAX_HALF + 1) return fail(RFR_EOVERFLOW, "too many elements for the search tables");
-    size_t need = recombine_workspace(P.n);
-    rfr_status st = ensure_workspace(ctx, s, need);
-    if (st != RFR_OK) return st;
+    rfr_status st = RFR_OK;
+    if (s.ws_bytes < recombine_workspace(P.n) && chunk_bits(P.n, s.ws_bytes) < 0) {
+        // grow within the budget; a search larger than the budget streams half A
+        const size_t avail = ctx->budget - (ctx->mem_used - s.ws_bytes);
+        const size_t need = choose_workspace(P.n, avail);
+        if (!need) return fail(RFR_ENOMEM, "search tables exceed the memory budget even when chunked");
+        st = ensure_workspace(ctx, s, need);
+        if (st != RFR_OK) return st;
+    }
     std::string err;
     const bool prof = ctx->profiling && !ctx->serving;
     st = enqueue_recombine(P.w.data(), P.n, P.t_lo, P.t_hi, s.ws, s.ws_bytes, s.stream, s.cand_dev, s.cap,
@@ -177,6 +199,7 @@ rfr_status rfr_create(int device, size_t mem_budget_bytes, rfr_ctx **out) {
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
         return fail(RFR_EDEVICE, "no such HIP device");
     if (hipSetDevice(device) != hipSuccess) return fail(RFR_EDEVICE, "hipSetDevice failed");
+    tuning_autoload();
     rfr_ctx *ctx = new (std::nothrow) rfr_ctx();
     if (!ctx) return fail(RFR_ENOMEM, "context allocation failed");
     ctx->device = device;
@@ -261,6 +284,14 @@ rfr_status rfr_weights(const int64_t *coeffs, int degree, uint64_t *w_out, int32
 }
 
 size_t rfr_recombine_workspace_bytes(int n) { return recombine_workspace(n); }
+
+size_t rfr_recombine_min_workspace_bytes(int n) {
+    if (n < 2 || n > 2 * dev::MAX_HALF + 1) return 0;
+    int na, nb;
+    split_halves(n, na, nb);
+    JobPlan P;
+    return plan_job(na - std::min(na, dev::MAX_CHUNK_BITS), nb, P, dev::KCAP_MAX);
+}
 
 rfr_status rfr_recombine_dev(const uint64_t *w_host, int n, uint64_t t_lo, uint64_t t_hi, void *workspace,
                              size_t ws_bytes, void *hip_stream, uint64_t *cand_dev, uint64_t cap,

@@ -78,6 +78,8 @@ rfr_status ensure_workspace(rfr_ctx *ctx, Slot &s, size_t need);
 rfr_status slot_init(rfr_ctx *ctx, Slot &s);
 void slot_free(rfr_ctx *ctx, Slot &s);
 rfr_status search_on_slot(rfr_ctx *ctx, Slot &s, const Prepared &P, std::vector<Pat> &cands);
+size_t choose_workspace(int n, size_t avail);
+void tuning_autoload();
 rfr_status factor_on_slot(rfr_ctx *ctx, Slot &s, const int64_t *coeffs, int degree, rfr_result **out);
 void batch_release(rfr_ctx *ctx);
 StageEvents *profile_events(rfr_ctx *ctx, int k);

@@ -39,6 +39,7 @@ constexpr int KCAP_MAX = 4096;    // key pairs held per search
 constexpr int RBITS_LOG = 16;     // LDS bitmap of candidate-key prefixes
 constexpr int RBITS = 1 << RBITS_LOG;
 constexpr int MAX_HALF = 34;      // elements per half (2^34 keys)
+constexpr int MAX_CHUNK_BITS = 8; // half A streamed in at most 2^8 chunks
 constexpr int RECOVER_FEW = 64;   // candidate keys handled by the meet-in-the-middle recovery
 constexpr int SPT4 = 16;          // Gray steps per thread in that recovery
 
@@ -70,6 +71,11 @@ struct JobArgs {
     uint64_t *out_count;
     uint64_t cap;
     uint32_t *flags;            // bit 0: sort overflow, bit 1: join fallback used
+    // chunked half A: every enumerated key of half h gets kbase[h] added and
+    // every recovered pattern pbase[h] or-ed in (the chunk's fixed high bits)
+    uint64_t kbase[2];
+    uint64_t pbase[2];
+    int first_chunk;            // 1: this launch starts the pattern count at 0
 };
 
 // Stages of the pipeline (kernel launches), in launch order.
@@ -128,6 +134,15 @@ struct SmallJob {
 };
 
 
+// Autotuned digit split for one size class (log2 of the larger half).
+struct Tune {
+    int b1;       // level-1 digit bits (-1: default)
+    int sub_log;  // log2 of the mean keys per sub-bucket (10 or 11; -1: default)
+    double ms;    // time measured by the autotuner
+};
+void set_tune(int lg, Tune t);
+Tune get_tune(int lg);
+
 // Workspace bytes for a search of half sizes (na, nb); nb < 0 = one half only.
 uint64_t plan_job(int na, int nb, JobPlan &P, uint64_t kcap);
 // Lay the job out at ws and fill its kernel arguments (B' weights negated).
@@ -135,6 +150,8 @@ void build_job(JobPlan &P, char *ws, const uint64_t *wa, const uint64_t *wb, uin
                uint64_t *out, uint64_t *out_count, uint64_t cap, dev::JobArgs &J);
 hipError_t launch_small(const SmallJob *jobs_dev, int njobs, uint32_t *queue_dev, int grid, hipStream_t st);
 size_t recombine_workspace(int n);
+// Chunk bits of half A so that a search over n weights fits ws_bytes (-1: none).
+int chunk_bits(int n, size_t ws_bytes);
 size_t expand_workspace(int m);
 
 rfr_status enqueue_recombine(const uint64_t *w, int n, uint64_t t_lo, uint64_t t_hi, void *ws,

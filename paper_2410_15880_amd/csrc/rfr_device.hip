@@ -148,7 +148,7 @@ __global__ void k_init(JobArgs Jarg, Multi M) {
         *J.kp_count = 0;
         J.rec_count[0] = 0;
         J.rec_count[1] = 0;
-        if (J.out_count) *J.out_count = 0;
+        if (J.out_count && J.first_chunk) *J.out_count = 0;
         *J.flags = 0;
     }
 }
@@ -188,7 +188,7 @@ __global__ __launch_bounds__(NT1) void k_enum(JobArgs Jarg, Multi M) {
     }
     __syncthreads();
 
-    uint64_t slo = 0;
+    uint64_t slo = J.kbase[blockIdx.y];
     for (int i = 0; i < H.L; ++i)
         if ((tid >> i) & 1) slo += s_w[i];
     const uint64_t h0 = (uint64_t)wg * H.spw;
@@ -686,7 +686,7 @@ __global__ __launch_bounds__(NT1) void k_recover_few(JobArgs Jarg, Multi M) {
     if (tid < cnt) s_list[tid] = J.kp[2 * tid + half];
     __syncthreads();
     if (tid < nl) {
-        uint64_t v = 0;
+        uint64_t v = J.kbase[half];
         for (int i = 0; i < H.L; ++i)
             if ((tid >> i) & 1) v += s_w[i];
         s_v[tid] = v;
@@ -722,7 +722,7 @@ __global__ __launch_bounds__(NT1) void k_recover_few(JobArgs Jarg, Multi M) {
             bool dup = false;  // the same key listed twice: record it once
             for (uint32_t c2 = 0; c2 < c && !dup; ++c2) dup = s_list[c2] == key;
             for (int q = lo; !dup && q < nl && s_sorted[q] == x; ++q) {
-                const uint64_t pat = (uint64_t)s_lane[q] | (g << H.L);
+                const uint64_t pat = ((uint64_t)s_lane[q] | (g << H.L)) | J.pbase[half];
                 const uint32_t r = atomicAdd(&J.rec_count[half], 1u);
                 if (r < J.kcap) {
                     J.rec[((size_t)half * J.kcap + r) * 2] = key;
@@ -772,7 +772,7 @@ __global__ __launch_bounds__(NT1) void k_recover(JobArgs Jarg, Multi M) {
     }
     __syncthreads();
 
-    uint64_t slo = 0;
+    uint64_t slo = J.kbase[half];
     for (int i = 0; i < H.L; ++i)
         if ((tid >> i) & 1) slo += s_w[i];
     const uint64_t h0 = (uint64_t)wg * H.spw;
@@ -788,7 +788,7 @@ __global__ __launch_bounds__(NT1) void k_recover(JobArgs Jarg, Multi M) {
             if ((s_bits[hb >> 5] >> (hb & 31)) & 1) {
                 for (uint32_t i = 0; i < cnt; ++i) {
                     if (s_list[i] == key) {
-                        const uint64_t pat = (uint64_t)tid | (g << H.L);
+                        const uint64_t pat = ((uint64_t)tid | (g << H.L)) | J.pbase[half];
                         const uint32_t r = atomicAdd(&J.rec_count[half], 1u);
                         if (r < J.kcap) {
                             J.rec[((size_t)half * J.kcap + r) * 2] = key;
@@ -818,10 +818,11 @@ __global__ __launch_bounds__(NT1) void k_pairs(JobArgs Jarg, Multi M) {
     if (!pick<MULTI>(Jarg, M, ST_PAIRS, Jp, bx)) return;
     const JobArgs &J = *Jp;
     const uint64_t cnt = *J.kp_count;
+    const uint64_t carry = *J.out_count;  // patterns of earlier chunks of half A
     __shared__ uint64_t s_total;
-    if (threadIdx.x == 0) s_total = 0;
+    if (threadIdx.x == 0) s_total = carry;
     __syncthreads();
-    if (cnt > J.kcap) {
+    if (cnt > J.kcap || carry == ~0ull) {
         if (threadIdx.x == 0) *J.out_count = ~0ull;
         return;
     }
@@ -872,11 +873,40 @@ static void plan_half(int m, HalfPlan &h) {
 // Digit split of the 2^LB sub-buckets (mean 2^SUB_LOG keys of the larger half
 // each): up to 16 bits as 8 + 8 (level-1 runs of ~16 keys per K1 tile, level-2
 // runs of ~16 keys per K2 tile); beyond that both levels grow, level 1 first.
+// Tuning table (size class log2 N -> level-1 bits and sub-bucket size), set
+// by the autotuner or loaded from its file; -1 entries use the defaults below.
+static Tune g_tune[MAX_HALF + 1] = {};
+static bool g_tune_init = false;
+static void tune_defaults() {
+    if (g_tune_init) return;
+    for (auto &t : g_tune) t = Tune{-1, -1, 0.0};
+    g_tune_init = true;
+}
+void set_tune(int lg, Tune t) {
+    tune_defaults();
+    if (lg >= 0 && lg <= MAX_HALF) g_tune[lg] = t;
+}
+Tune get_tune(int lg) {
+    tune_defaults();
+    return (lg >= 0 && lg <= MAX_HALF) ? g_tune[lg] : Tune{-1, -1, 0.0};
+}
+
 static void plan_bits(uint64_t nmax, int &B1, int &B2) {
     int lg = 0;
     while ((1ull << lg) < nmax) ++lg;
-    int LB = lg > SUB_LOG ? lg - SUB_LOG : 0;
+    const Tune tn = get_tune(lg);
+    const int sub = (tn.sub_log == 10 || tn.sub_log == 11) ? tn.sub_log : SUB_LOG;
+    int LB = lg > sub ? lg - sub : 0;
     if (LB > MAXB1_LOG + MAXB2_LOG) LB = MAXB1_LOG + MAXB2_LOG;
+    if (tn.b1 >= 0) {
+        B1 = std::min(std::min(tn.b1, LB), MAXB1_LOG);
+        B2 = LB - B1;
+        if (B2 > MAXB2_LOG) {
+            B1 += B2 - MAXB2_LOG;
+            B2 = MAXB2_LOG;
+        }
+        return;
+    }
     if (LB <= 16) {
         B1 = LB < 8 ? LB : 8;
         B2 = LB - B1;
@@ -958,6 +988,7 @@ void build_job(JobPlan &P, char *ws, const uint64_t *wa, const uint64_t *wb, uin
     J.out = out;
     J.out_count = out_count;
     J.cap = cap;
+    J.first_chunk = 1;
 }
 
 // Blocks (x) of every stage for one job; the y dimension is the half.
@@ -1019,6 +1050,19 @@ static hipError_t launch_all(const JobArgs &J, const Multi &M, const uint32_t *g
     return hipGetLastError();
 }
 
+// Chunks of half A needed to fit ws_bytes: the smallest c such that a search
+// over half A's low n_a - c weights (the top c fixed per chunk) plus all of
+// half B' fits (c <= MAX_CHUNK_BITS).  Returns -1 if none fits.
+int chunk_bits(int n, size_t ws_bytes) {
+    int na, nb;
+    split_halves(n, na, nb);
+    for (int c = 0; c <= std::min(na, MAX_CHUNK_BITS); ++c) {
+        JobPlan P;
+        if (plan_job(na - c, nb, P, KCAP_MAX) <= ws_bytes) return c;
+    }
+    return -1;
+}
+
 rfr_status enqueue_recombine(const uint64_t *w, int n, uint64_t t_lo, uint64_t t_hi, void *ws,
                              size_t ws_bytes, hipStream_t st, uint64_t *cand, uint64_t cap,
                              uint64_t *count, StageEvents *ev, std::string &err) {
@@ -1036,23 +1080,37 @@ rfr_status enqueue_recombine(const uint64_t *w, int n, uint64_t t_lo, uint64_t t
     }
     int na, nb;
     split_halves(n, na, nb);
-    JobPlan P;
-    uint64_t need = plan_job(na, nb, P, KCAP_MAX);
-    if (ws_bytes < need) {
+    const int c = chunk_bits(n, ws_bytes);
+    if (c < 0) {
         err = "rfr_recombine_dev: workspace too small";
         return RFR_ENOMEM;
     }
+    const int ma = na - c;  // weights of half A enumerated per chunk
+    JobPlan P;
+    plan_job(ma, nb, P, KCAP_MAX);
     std::vector<uint64_t> wneg(nb);
     for (int i = 0; i < nb; ++i) wneg[i] = 0 - w[na + i];
-    JobArgs J;
-    build_job(P, (char *)ws, w, wneg.data(), t_lo, t_hi, cand, count, cap, J);
-    J.kcap = std::min<uint64_t>(cap + 1, KCAP_MAX);
     uint32_t grids[NSTAGES];
     stage_blocks(P, grids);
     Multi M{nullptr, nullptr, 0};
-    if (launch_all<false>(J, M, grids, 2, P.B1, P.B2, true, nullptr, st, ev) != hipSuccess) {
-        err = "kernel launch failed";
-        return RFR_EDEVICE;
+    const uint64_t nchunks = 1ull << c;
+    for (uint64_t t = 0; t < nchunks; ++t) {
+        JobArgs J;
+        build_job(P, (char *)ws, w, wneg.data(), t_lo, t_hi, cand, count, cap, J);
+        J.kcap = std::min<uint64_t>(cap + 1, KCAP_MAX);
+        uint64_t kb = 0;
+        for (int i = 0; i < c; ++i)
+            if ((t >> i) & 1) kb += w[ma + i];
+        J.kbase[0] = kb;
+        J.pbase[0] = t << ma;
+        J.first_chunk = t == 0;
+        // half B' is enumerated, partitioned and tile-sorted by the first chunk
+        // only; later chunks redo half A and join against the resident B'
+        if (launch_all<false>(J, M, grids, t == 0 ? 2 : 1, P.B1, P.B2, true, nullptr, st,
+                              nchunks == 1 ? ev : nullptr) != hipSuccess) {
+            err = "kernel launch failed";
+            return RFR_EDEVICE;
+        }
     }
     return RFR_OK;
 }

@@ -105,7 +105,12 @@ static void serve_one(rfr_ctx *ctx, Request *r) {
         if (P.n > 2 * dev::MAX_HALF + 1) {
             st = fail(RFR_EOVERFLOW, "too many elements for the search tables");
         } else {
-            Slot *s = acquire_slot(ctx, recombine_workspace(P.n), st);
+            // admission size: the full tables, or a chunked layout (half A
+            // streamed) when the full tables would take over half the budget
+            size_t need = recombine_workspace(P.n);
+            if (need > ctx->budget / 2) need = choose_workspace(P.n, ctx->budget / 2);
+            Slot *s = need ? acquire_slot(ctx, need, st) : nullptr;
+            if (!need) st = fail(RFR_ENOMEM, "request tables do not fit the memory budget");
             if (s) {
                 t1 = now_ms();
                 st = search_on_slot(ctx, *s, P, cands);

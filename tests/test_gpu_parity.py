@@ -187,3 +187,46 @@ def test_repeat_runs_identical(R):
     first = R.recombine_dev(w, 40, 6)
     for _ in range(3):
         assert R.recombine_dev(w, 40, 6) == first
+
+
+# ------------------------------------------------------------------ chunked half A
+
+
+@pytest.mark.parametrize("n,frac", [(14, 0.6), (26, 0.5), (31, 0.3), (34, 0.0), (38, 0.45)])
+def test_chunked_search_matches_oracle(R, n, frac):
+    # a workspace between the minimum and the full one: half A is streamed in
+    # 2^c chunks against the resident B' half
+    rng = random.Random(500 + n)
+    w = planted_weights(rng, n, k_rel=5)
+    L = R.lib()
+    full = L.rfr_recombine_workspace_bytes(n)
+    mn = L.rfr_recombine_min_workspace_bytes(n)
+    ws = int(mn + frac * (full - mn))
+    assert mn <= ws < full
+    t_lo, t_hi = n + 9, 6
+    say("chunked n=%d ws=%d of %d" % (n, ws, full))
+    got = R.recombine_dev(w, t_lo, t_hi, cap=1 << 12, ws_bytes=ws)
+    want = O.search_brute(w, t_lo, t_hi) if n <= 26 else O.search_hs(w, t_lo, t_hi)
+    assert got == want
+
+
+def test_chunked_zero_weights_and_overflow(R):
+    L = R.lib()
+    n = 12
+    mn = L.rfr_recombine_min_workspace_bytes(n)
+    say("chunked zeros")
+    assert R.recombine_dev([0] * n, 0, 0, cap=4096, ws_bytes=mn) == list(range(1, 1 << (n - 1)))
+    with pytest.raises(R.RFRError) as e:
+        R.recombine_dev([0] * n, 0, 0, cap=100, ws_bytes=mn)
+    assert e.value.name == "RFR_ECANDIDATES"
+
+
+def test_small_budget_context_streams_half_a(R):
+    # a budget below the full tables of the degree-60 searches: the plain path
+    # streams half A and still returns the oracle's factorisations
+    g = json.load(open(os.path.join(HERE, "golden", "golden_mid.json")))["cases"]
+    with R.Context(0, mem_budget=800 << 10) as c:
+        for w in W.config_mid()[6:10]:
+            say("budget seed", w.seed)
+            e = g[str(w.seed)]
+            assert c.factor(w.coeffs) == (e["content"], [tuple(f) for f in e["factors"]])
