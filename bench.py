@@ -35,6 +35,42 @@ STAGE_KERNEL = {"count": "k_enum<true>", "scan": "k_scan_cols+k_scan_buckets",
                 "recover": "k_recover+k_pairs"}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_search_kernels_degree100x16.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2410_15880_amd", "csrc", f) for f in ("rfr_device.hip", "rfr_device.h")]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(stage):
+    """HBM bytes per launch of a stage's kernel from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by what the same counters read
+    for a copy of known size), or None when the kernels changed since."""
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    kv, kern = {}, {}
+    for ln in lines:
+        p = ln.split()
+        if not p or p[0].startswith("#"):
+            continue
+        if p[0] == "stage" and len(p) >= 6:
+            kern[p[1]] = (float(p[3]), float(p[5]))  # stage <name> fetch_kib <x> write_kib <y>
+        elif len(p) == 2:
+            kv[p[0]] = p[1]
+    if kv.get("source_sha256") != kernel_source_hash() or stage not in kern:
+        return None
+    fk, wk = kern[stage]
+    return int((fk * float(kv["fetch_scale"]) + wk * float(kv["write_scale"])) * 1024)
+
+
 def host_info():
     model = platform.processor() or ""
     try:
@@ -228,7 +264,7 @@ def main():
     achieved = alg_bytes / (stage_avg[dom] / 1000.0) / 1e9 if stage_avg[dom] > 0 else 0.0
     if STAGE_BYTES_PER_KEY[dom] > 0:
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
                     "kernel": STAGE_KERNEL[dom], "avg_launch_ms": round(stage_avg[dom], 4),
                     "alg_bytes_per_launch": int(alg_bytes)}
     else:

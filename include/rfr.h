@@ -167,7 +167,10 @@ rfr_status rfr_profile_read(rfr_ctx *ctx, rfr_profile_t *out);
  * creation. */
 rfr_status rfr_autotune(rfr_ctx *ctx, int lg_lo, int lg_hi, const char *path_out);
 
-/* Install a table written by rfr_autotune. */
+/* Install a table written by rfr_autotune ("lg b1 sub_log ms" lines; a line
+ * "lg -1 -1 0" returns class lg to the fixed rule).  Affects the workspace
+ * size and speed of later searches, never their results; not concurrent with
+ * searches. */
 rfr_status rfr_load_tuning(const char *path);
 
 /* ------------------------------------------------------------------ results */

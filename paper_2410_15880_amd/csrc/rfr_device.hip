@@ -426,72 +426,136 @@ __device__ void edge_scan(const JobArgs &J, uint64_t a, uint32_t s, uint32_t ns,
     });
 }
 
+// Exclusive prefix maximum across the workgroup of two 32-bit values packed in
+// one 64-bit word (low and high halves taken separately); 0 is the identity.
+__device__ __forceinline__ uint64_t max2(uint64_t x, uint64_t y) {
+    const uint32_t lo = max((uint32_t)x, (uint32_t)y), hi = max((uint32_t)(x >> 32), (uint32_t)(y >> 32));
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+template <int NTH>
+__device__ __forceinline__ uint64_t block_excl_max2(uint64_t v, uint64_t *s_tmp) {
+    constexpr int NW = NTH / 64;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint64_t inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t t = __shfl_up(inc, o, 64);
+        if (lane >= o) inc = max2(inc, t);
+    }
+    uint64_t ex = __shfl_up(inc, 1, 64);
+    if (lane == 0) ex = 0;
+    if (lane == 63) s_tmp[wv] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t acc = 0;
+        for (int i = 0; i < NW; ++i) {
+            const uint64_t t = s_tmp[i];
+            s_tmp[i] = acc;
+            acc = max2(acc, t);
+        }
+    }
+    __syncthreads();
+    ex = max2(ex, s_tmp[wv]);
+    __syncthreads();
+    return ex;
+}
+
 // Gather sub-bucket (b, d) of NH halves into register slots: key q of half h
 // (q = tid + k*NT3) lands in kk[h][k].  The bucket's tiles are taken in chunks
-// of MAXT: each thread reads one tile's digit-d segment bounds per half, one
-// packed block scan (half 0 low 32 bits, half 1 high) gives the segments' key
-// offsets, an LDS tile map q -> tile lets every thread address its keys
-// directly, and all slot loads of a chunk are in flight together.  Returns
-// the key counts; counts beyond CAP3 are reported but not loaded.
+// of MAXT.  Thread t holds tile t's digit-d segment bounds (per half; preloaded
+// by the caller when the bucket has at most MAXT tiles); one packed block scan
+// gives the segments' key offsets.  The tile map q -> tile is built in LDS
+// without walking the segments: each non-empty segment puts its tile number at
+// its first offset, and a prefix maximum over the map (tiles come in offset
+// order) fills the rest; every thread owns 12 consecutive map bytes per half.
+// Each tile's key offset from the bucket start minus its first slot goes to
+// LDS, so a slot's address is one LDS read and an add, and all slot loads of a
+// chunk are in flight together.  Buckets below 2^29 keys keep byte offsets in
+// 32 bits (larger ones are routed to the fallback by the caller).  Returns the
+// key counts; counts beyond CAP3 are reported but not loaded.
 template <int NH>
-__device__ __forceinline__ void gather_regs(const JobArgs &J, int b, int d, uint64_t (&kk)[2][KP3],
-                                            uint32_t (&n)[2], uint32_t (*s_st)[MAXT], uint32_t (*s_off)[MAXT + 1],
-                                            uint8_t (*s_tmap)[CAP3], uint64_t *s_tmp) {
+__device__ __forceinline__ void gather_regs(const JobArgs &J, int d, const SubRef (&r)[2], bool pre,
+                                            const uint32_t (&pst)[2], const uint32_t (&pen)[2],
+                                            uint64_t (&kk)[2][KP3], uint32_t (&n)[2], uint32_t (*s_src)[MAXT],
+                                            uint32_t *s_mapw, uint64_t *s_tmp) {
+    static_assert(CAP3 == NT3 * 12, "the map scan gives every thread 12 bytes per half");
+    constexpr int MW = CAP3 / 4;  // map words per half
     const int tid = threadIdx.x;
-    SubRef r[2];
+    uint8_t *s_map = (uint8_t *)s_mapw;
     uint32_t nt[2] = {0, 0};
 #pragma unroll
-    for (int h = 0; h < NH; ++h) {
-        r[h] = sub_ref(J.h[h], b);
-        nt[h] = r[h].t1 - r[h].t0;
-    }
+    for (int h = 0; h < NH; ++h) nt[h] = r[h].t1 - r[h].t0;
     const uint32_t ntmax = max(nt[0], NH > 1 ? nt[1] : 0u);
     uint32_t base[2] = {0, 0};
     for (uint32_t c0 = 0; c0 < ntmax; c0 += MAXT) {
-        unsigned long long mine = 0;
-        uint32_t len[2] = {0, 0};
+        uint32_t len[2] = {0, 0}, st[2] = {0, 0};
 #pragma unroll
         for (int h = 0; h < NH; ++h) {
             const HalfArgs &H = J.h[h];
             const uint32_t t = c0 + tid;
             if (t < nt[h]) {
-                const uint32_t st = H.digstart[(size_t)d * H.ntile2_max + r[h].t0 + t];
-                const uint32_t en = H.digstart[(size_t)(d + 1) * H.ntile2_max + r[h].t0 + t];
-                s_st[h][tid] = st;
-                len[h] = en - st;
+                if (pre) {
+                    st[h] = pst[h];
+                    len[h] = pen[h] - pst[h];
+                } else {
+                    st[h] = H.digstart[(size_t)d * H.ntile2_max + r[h].t0 + t];
+                    len[h] = H.digstart[(size_t)(d + 1) * H.ntile2_max + r[h].t0 + t] - st[h];
+                }
             }
         }
-        mine = (unsigned long long)len[0] | ((unsigned long long)len[1] << 32);
+        for (int i = tid; i < NH * MW; i += NT3) s_mapw[i] = 0;
         uint64_t tot;
-        const unsigned long long pre = block_excl_scan<NT3>(mine, s_tmp, &tot);
+        const uint64_t pre_off = block_excl_scan<NT3>((uint64_t)len[0] | ((uint64_t)len[1] << 32), s_tmp, &tot);
         const uint32_t cl[2] = {(uint32_t)tot, (uint32_t)(tot >> 32)};
 #pragma unroll
         for (int h = 0; h < NH; ++h) {
-            s_off[h][tid] = h ? (uint32_t)(pre >> 32) : (uint32_t)pre;
-            if (tid == 0) s_off[h][MAXT] = cl[h];
+            const uint32_t pos = base[h] + (h ? (uint32_t)(pre_off >> 32) : (uint32_t)pre_off);
+            if (len[h] > 0) {
+                if (pos < CAP3) s_map[h * CAP3 + pos] = (uint8_t)tid;
+                s_src[h][tid] = (c0 + tid) * (uint32_t)T2 + st[h] - pos;
+            }
         }
         __syncthreads();
-        const int wv = tid >> 6, lane = tid & 63;
+        // prefix maximum over the map
+        uint32_t w[2][3];
+        uint64_t mx = 0;
 #pragma unroll
         for (int h = 0; h < NH; ++h) {
-            const uint32_t cn = nt[h] > c0 ? min((uint32_t)MAXT, nt[h] - c0) : 0u;
-            for (uint32_t t = wv; t < cn; t += NT3 / 64) {
-                const uint32_t o = s_off[h][t], e = (t + 1 < cn) ? s_off[h][t + 1] : cl[h];
-                for (uint32_t q = o + lane; q < e; q += 64)
-                    if (base[h] + q < CAP3) s_tmap[h][base[h] + q] = (uint8_t)t;
+            uint32_t m = 0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                w[h][j] = s_mapw[h * MW + tid * 3 + j];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) m = max(m, (w[h][j] >> (8 * k)) & 0xFFu);
+            }
+            mx |= (uint64_t)m << (32 * h);
+        }
+        const uint64_t px = block_excl_max2<NT3>(mx, s_tmp);
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+            uint32_t m = (uint32_t)(px >> (32 * h));
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                uint32_t o = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    m = max(m, (w[h][j] >> (8 * k)) & 0xFFu);
+                    o |= m << (8 * k);
+                }
+                s_mapw[h * MW + tid * 3 + j] = o;
             }
         }
         __syncthreads();
 #pragma unroll
         for (int h = 0; h < NH; ++h) {
-            const HalfArgs &H = J.h[h];
+            const char *bk = (const char *)(J.h[h].keys + r[h].pos0);
 #pragma unroll
             for (int k = 0; k < KP3; ++k) {
                 const uint32_t q = tid + k * NT3;
                 if (q >= base[h] && q < base[h] + cl[h] && q < CAP3) {
-                    const uint32_t t = s_tmap[h][q];
-                    kk[h][k] = __builtin_nontemporal_load(
-                        &H.keys[r[h].pos0 + (uint64_t)(c0 + t) * T2 + s_st[h][t] + (q - base[h] - s_off[h][t])]);
+                    const uint32_t boff = (s_src[h][s_map[h * CAP3 + q]] + q) * 8u;
+                    kk[h][k] = __builtin_nontemporal_load((const uint64_t *)(bk + boff));
                 }
             }
             base[h] += cl[h];
@@ -567,18 +631,299 @@ __device__ void join_fallback(const JobArgs &J, uint32_t s, uint32_t NS, int b, 
     }
 }
 
+// Exact band probe of B' bins (fallback when the semi-join's lists overflow):
+// s_b holds the sub-bucket's B' keys counting-sorted by the LB3-bit digit.
+__device__ __forceinline__ void probe_bins(const JobArgs &J, uint64_t a, uint64_t clo, uint64_t chi, uint64_t wlo,
+                                           uint64_t whi, int sh3, const uint64_t *s_b, const uint32_t *s_bin) {
+    const uint32_t b0 = dig(clo, sh3, NB3 - 1), b1 = dig(chi, sh3, NB3 - 1);
+    const uint32_t e = s_bin[b1 + 1];
+    for (uint32_t i = s_bin[b0]; i < e; ++i) {
+        const uint64_t bk = s_b[i];
+        if (bk >= wlo && bk <= whi) emit_pair(J, a, bk);
+    }
+}
+
+// Append `cnt` items of this thread to an LDS list whose length is *counter:
+// returns the index of the thread's first item.  One LDS atomic per
+// wavefront; every lane of the wavefront must call it.
+__device__ __forceinline__ uint32_t wave_append(uint32_t *counter, uint32_t cnt) {
+    const int lane = threadIdx.x & 63;
+    uint32_t inc = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += t;
+    }
+    const uint32_t total = __shfl(inc, 63, 64);
+    uint32_t base = 0;
+    if (lane == 63 && total) base = atomicAdd(counter, total);
+    return __shfl(base, 63, 64) + inc - cnt;
+}
+
+// Cell bitmaps of the semi-join.  A cell is at least as wide as the window,
+// so the window [a - t_hi, a + t_lo] of a key in cell c meets cell c and, only
+// when a lies within t_hi of the cell's low edge (t_lo of its high edge), cell
+// c - 1 (c + 1) -- a case of probability about window / cell width.
+__device__ __forceinline__ void mark1(uint32_t *bm, uint32_t c) { atomicOr(&bm[c >> 5], 1u << (c & 31)); }
+
+__device__ __forceinline__ bool bit(const uint32_t *bm, uint32_t c) { return (bm[c >> 5] >> (c & 31)) & 1u; }
+
+// Edge flags of key a in its cell (cell width 2^shc).
+__device__ __forceinline__ void cell_edges(uint64_t a, int shc, uint64_t t_lo, uint64_t t_hi, bool &lo, bool &hi) {
+    const uint64_t off = a & ((1ull << shc) - 1);
+    lo = off < t_hi;
+    hi = ((1ull << shc) - 1 - off) < t_lo;
+}
+
+// Does a's window meet a marked cell?  Marks those cells in `mk` if given.
+template <uint32_t NC>
+__device__ __forceinline__ bool window_hits(const uint32_t *bm, uint32_t c, bool lo, bool hi) {
+    return bit(bm, c) || (lo && c > 0 && bit(bm, c - 1)) || (hi && c < NC - 1 && bit(bm, c + 1));
+}
+
+template <uint32_t NC>
+__device__ __forceinline__ void mark_window(uint32_t *bm, uint32_t c, bool lo, bool hi) {
+    mark1(bm, c);
+    if (lo && c > 0) mark1(bm, c - 1);
+    if (hi && c < NC - 1) mark1(bm, c + 1);
+}
+
+// LDS of a sorting (expansion) K3 workgroup: the sub-bucket's keys and bins.
+struct SortLds {
+    uint64_t b[CAP3];
+    uint32_t bin[NB3 + 1];
+    uint32_t src[2][MAXT];
+    uint32_t mapw[2 * CAP3 / 4];
+    uint64_t tmp[NT3 / 64 + 2];
+    uint32_t nl[2];
+};
+
+// LDS of one joining K3 workgroup, sized so that six workgroups fit a CU.
+// `u` holds either the semi-join's bitmap and two lists or, on the exact
+// fallback, a chunk of B' keys.
+struct JoinLds {
+    static constexpr uint32_t NWD = (1u << CB3) / 32;  // bitmap words
+    union {
+        struct {
+            uint32_t bm[NWD];
+            uint64_t la[LCAP3];
+            uint64_t lb[LCAP3];
+        } sj;
+        uint64_t keys[FB3];
+    } u;
+    uint32_t src[2][MAXT];
+    uint32_t mapw[2 * CAP3 / 4];
+    uint64_t tmp[NT3 / 64 + 2];
+    uint32_t nl[2];
+};
+
+// Exact join of one sub-bucket without the semi-join (window wider than a
+// cell, or clustered keys overflowing a list): B' is staged through LDS in
+// chunks of FB3 keys and every a tests every staged b'.  Quadratic, only for
+// such inputs.
+__device__ __forceinline__ void join_exact(const JobArgs &J, const uint64_t (&kk)[2][KP3], uint32_t na, uint32_t nb,
+                                        uint64_t *s_keys) {
+    const int tid = threadIdx.x;
+    const uint64_t t_lo = J.t_lo, t_hi = J.t_hi;
+    for (uint32_t c0 = 0; c0 < nb; c0 += FB3) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KP3; ++k) {
+            const uint32_t q = tid + k * NT3;
+            if (q >= c0 && q < nb && q < c0 + FB3) s_keys[q - c0] = kk[1][k];
+        }
+        __syncthreads();
+        const uint32_t cn = min((uint32_t)FB3, nb - c0);
+#pragma unroll
+        for (int k = 0; k < KP3; ++k) {
+            if (tid + k * NT3 >= na) continue;
+            const uint64_t a = kk[0][k];
+            const uint64_t wlo = a >= t_hi ? a - t_hi : 0;
+            const uint64_t whi = a <= ~0ull - t_lo ? a + t_lo : ~0ull;
+            for (uint32_t i = 0; i < cn; ++i) {
+                const uint64_t bk = s_keys[i];
+                if (bk >= wlo && bk <= whi) emit_pair(J, a, bk);
+            }
+        }
+    }
+}
+
+// Semi-join of one sub-bucket s = (b, d) whose keys are in register slots
+// (see k_join, steps 2-4).
+__device__ __forceinline__ void join_semi(const JobArgs &J, uint32_t s, int b, int d, const uint64_t (&kk)[2][KP3],
+                                          uint32_t na, uint32_t nb, JoinLds &L) {
+    constexpr uint32_t NC = 1u << CB3;  // cells
+    constexpr uint32_t NWD = JoinLds::NWD;
+    const int LB = J.B1 + J.B2;
+    const uint32_t NS = 1u << LB;
+    const int shc = 64 - LB - CB3;
+    const int tid = threadIdx.x;
+    uint32_t *bm = L.u.sj.bm;
+    uint64_t *LA = L.u.sj.la;
+    uint64_t *LBl = L.u.sj.lb;
+    if (na > CAP3 || nb > CAP3) {
+        join_fallback(J, s, NS, b, d);
+        return;
+    }
+    __syncthreads();  // bitmap zeroing visible even when the gather had no chunk
+
+    const uint64_t s_lo = LB == 0 ? 0 : ((uint64_t)s << (64 - LB));
+    const uint64_t s_hi = LB == 0 ? ~0ull : (s_lo + ((1ull << (64 - LB)) - 1));
+    const uint64_t t_lo = J.t_lo, t_hi = J.t_hi;
+    const uint64_t cellw = 1ull << shc;
+    const bool fast = t_lo <= cellw && t_hi <= cellw;
+    bool lists = false;
+    if (fast) {
+        // B' marks its cells
+#pragma unroll
+        for (int k = 0; k < KP3; ++k)
+            if (tid + k * NT3 < nb) mark1(bm, dig(kk[1][k], shc, NC - 1));
+        __syncthreads();
+        // A keys whose window meets a marked cell
+        uint32_t hits = 0;
+#pragma unroll
+        for (int k = 0; k < KP3; ++k) {
+            if (tid + k * NT3 >= na) continue;
+            bool lo, hi;
+            cell_edges(kk[0][k], shc, t_lo, t_hi, lo, hi);
+            if (window_hits<NC>(bm, dig(kk[0][k], shc, NC - 1), lo, hi)) hits |= 1u << k;
+        }
+        uint32_t o = wave_append(&L.nl[0], __popc(hits));
+#pragma unroll
+        for (int k = 0; k < KP3; ++k)
+            if ((hits >> k) & 1u) {
+                if (o < LCAP3) LA[o] = kk[0][k];
+                ++o;
+            }
+        __syncthreads();
+        const uint32_t nla = L.nl[0];
+        if (nla <= LCAP3) {
+            // the same bitmap, now of the cells LA's windows meet; B' keys in them
+            for (uint32_t i = tid; i < NWD; i += NT3) bm[i] = 0;
+            __syncthreads();
+            for (uint32_t i = tid; i < nla; i += NT3) {
+                bool lo, hi;
+                cell_edges(LA[i], shc, t_lo, t_hi, lo, hi);
+                mark_window<NC>(bm, dig(LA[i], shc, NC - 1), lo, hi);
+            }
+            __syncthreads();
+            uint32_t bh = 0;
+#pragma unroll
+            for (int k = 0; k < KP3; ++k)
+                if (tid + k * NT3 < nb && bit(bm, dig(kk[1][k], shc, NC - 1))) bh |= 1u << k;
+            uint32_t ob = wave_append(&L.nl[1], __popc(bh));
+#pragma unroll
+            for (int k = 0; k < KP3; ++k)
+                if ((bh >> k) & 1u) {
+                    if (ob < LCAP3) LBl[ob] = kk[1][k];
+                    ++ob;
+                }
+            __syncthreads();
+        }
+        const uint32_t nlb = L.nl[1];
+        lists = nla <= LCAP3 && nlb <= LCAP3;
+        if (lists) {
+            // every pair of the lists: each wavefront takes LA entries, its
+            // lanes hold LB entries
+            const int lane = tid & 63, wv = tid >> 6;
+            for (uint32_t j0 = 0; j0 < nlb; j0 += 64) {
+                const uint32_t j = j0 + lane;
+                const bool valid = j < nlb;
+                const uint64_t bk = valid ? LBl[j] : 0;
+#pragma unroll 4
+                for (uint32_t i = wv; i < nla; i += NT3 / 64) {
+                    const uint64_t a = LA[i];
+                    const uint64_t wlo = a >= t_hi ? a - t_hi : 0;
+                    const uint64_t whi = a <= ~0ull - t_lo ? a + t_lo : ~0ull;
+                    if (valid && bk >= wlo && bk <= whi) emit_pair(J, a, bk);
+                }
+            }
+        }
+    }
+    if (!lists) join_exact(J, kk, na, nb, L.u.keys);
+    // windows reaching past this sub-bucket (or wrapping past 0); with
+    // windows no wider than a cell only keys in the first or last cell can
+#pragma unroll
+    for (int k = 0; k < KP3; ++k) {
+        if (tid + k * NT3 >= na) continue;
+        const uint64_t a = kk[0][k];
+        if (fast) {
+            const uint32_t c = dig(a, shc, NC - 1);
+            if (c != 0 && c != NC - 1) continue;
+        }
+        const bool low_edge = (a - s_lo) < t_hi;
+        const bool high_edge = (s_hi - a) < t_lo;
+        if (low_edge || high_edge) {
+            const uint64_t wlo = a >= t_hi ? a - t_hi : 0;
+            const uint64_t whi = a <= ~0ull - t_lo ? a + t_lo : ~0ull;
+            const uint32_t nlo = (s + NS - 1) & (NS - 1), nhi = (s + 1) & (NS - 1);
+            if (low_edge) edge_scan(J, a, s, nlo, wlo, whi);
+            if (high_edge && !(low_edge && nhi == nlo)) edge_scan(J, a, s, nhi, wlo, whi);
+        }
+    }
+}
+
+// Join of one sub-bucket s = (b, d) (see k_join).
+template <bool SORT_OUT, typename Lds>
+__device__ __forceinline__ void join_sub(const JobArgs &J, uint32_t s, int b, int d, const SubRef (&r)[2], bool pre,
+                                         const uint32_t (&pst)[2], const uint32_t (&pen)[2], uint64_t *sorted_out,
+                                         Lds &L) {
+    constexpr int NH = SORT_OUT ? 1 : 2;
+    const int tid = threadIdx.x;
+
+    if constexpr (SORT_OUT) {
+        for (int i = tid; i < NB3; i += NT3) L.bin[i] = 0;
+    } else {
+        for (uint32_t i = tid; i < JoinLds::NWD; i += NT3) L.u.sj.bm[i] = 0;
+        if (tid < 2) L.nl[tid] = 0;
+    }
+    uint32_t n[2];
+    if constexpr (SORT_OUT) {
+        uint64_t kk[2][KP3];
+        gather_regs<NH>(J, d, r, pre, pst, pen, kk, n, L.src, L.mapw, L.tmp);
+        const uint32_t na = n[0];
+        if (na > CAP3) {
+            if (tid == 0) atomicOr(J.flags, 1u);
+            return;
+        }
+        sort_slots(kk[0], na, 64 - (J.B1 + J.B2) - LB3, L.b, L.bin, L.tmp, true);
+        // output position: bucket start + keys of lower digits in every tile
+        uint64_t part = 0;
+        for (uint32_t t = r[0].t0 + tid; t < r[0].t1; t += NT3)
+            part += J.h[0].digstart[(size_t)d * J.h[0].ntile2_max + t];
+        uint64_t tot;
+        block_excl_scan<NT3>(part, L.tmp, &tot);
+        const uint64_t pos = r[0].pos0 + tot;
+        for (uint32_t i = tid; i < na; i += NT3) sorted_out[pos + i] = L.b[i];
+    } else {
+        uint64_t kk[2][KP3];
+        gather_regs<NH>(J, d, r, pre, pst, pen, kk, n, L.src, L.mapw, L.tmp);
+        join_semi(J, s, b, d, kk, n[0], n[1], L);
+    }
+}
+
 // K3: one sub-bucket s = (level-1 bucket b, level-2 digit d) per workgroup;
 // consecutive sub-buckets go to the same XCD so the tile-segment cache lines
-// they share meet in one L2.
+// they share meet in one L2.  Workgroups of NT3 threads with KP3 slots each
+// and a small LDS footprint, so that several of them share a CU: the join is bound
+// by the latency of its dependent loads (bucket extent, then segment bounds,
+// then keys), which only more workgroups in flight hide.
 //  1. gather both halves into register slots (gather_regs);
-//  2. LDS counting sort of B' by the LB3-bit digit below the sub-bucket prefix
-//     (one pass; with SORT_OUT the single half is fully sorted and written);
-//  3. band join: each a probes the one or two B' bins its window
-//     [a - t_hi, a + t_lo] overlaps inside the sub-bucket and emits every b'
-//     in it; a window reaching past the sub-bucket (or wrapping past 0) also
-//     scans the neighbour sub-bucket of B' from global memory (edge_scan).
+//  2. semi-join through an LDS bitmap over the sub-bucket's range cut into
+//     2^CB3 cells, each at least as wide as the window, so a pair's keys lie
+//     in the same or adjacent cells: every b' marks its cell and both
+//     neighbours; every a whose own cell is marked joins list LA; the bitmap
+//     is then rebuilt from LA's cells (dilated the same way) and every b'
+//     whose cell is marked joins list LB.  Random keys leave a few hundred
+//     entries in LA and a few dozen in LB, whose pairs are tested exactly;
+//  3. if a list overflows (clustered keys) or the window is wider than a
+//     cell, every a is tested against every b' instead (join_exact);
+//  4. a window reaching past the sub-bucket (or wrapping past 0) also scans
+//     the neighbour sub-bucket of B' from global memory (edge_scan).
+// With SORT_OUT the single half is fully sorted in LDS and written instead.
 template <bool SORT_OUT, bool MULTI>
-__global__ __launch_bounds__(NT3) void k_join(JobArgs Jarg, Multi M, uint64_t *sorted_out) {
+__global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k_join(JobArgs Jarg, Multi M,
+                                                                                        uint64_t *sorted_out) {
     constexpr int NH = SORT_OUT ? 1 : 2;
     const JobArgs *Jp;
     uint32_t s;
@@ -589,72 +934,40 @@ __global__ __launch_bounds__(NT3) void k_join(JobArgs Jarg, Multi M, uint64_t *s
     if (s >= NS) return;
     if (NS >= 64) s = (s & 7) * (NS >> 3) + (s >> 3);
     const int b = (int)(s >> J.B2), d = (int)(s & ((1u << J.B2) - 1));
-    const int sh3 = 64 - LB - LB3;
     const int tid = threadIdx.x;
+    __shared__ std::conditional_t<SORT_OUT, SortLds, JoinLds> L;
 
-    __shared__ uint64_t s_b[CAP3];
-    __shared__ uint32_t s_bin[NB3 + 1];
-    __shared__ uint32_t s_st[2][MAXT];
-    __shared__ uint32_t s_off[2][MAXT + 1];
-    __shared__ uint8_t s_tmap[2][CAP3];
-    __shared__ uint64_t s_tmp[NT3 / 64 + 2];
-
-    for (int i = tid; i < NB3; i += NT3) s_bin[i] = 0;
-    uint64_t kk[2][KP3];
-    uint32_t n[2];
-    gather_regs<NH>(J, b, d, kk, n, s_st, s_off, s_tmap, s_tmp);
-    const uint32_t na = n[0], nb = n[1];
-
-    if (SORT_OUT) {
-        if (na > CAP3) {
-            if (tid == 0) atomicOr(J.flags, 1u);
-            return;
-        }
-        sort_slots(kk[0], na, sh3, s_b, s_bin, s_tmp, true);
-        // output position: bucket start + keys of lower digits in every tile
-        const SubRef r = sub_ref(J.h[0], b);
-        uint64_t part = 0;
-        for (uint32_t t = r.t0 + tid; t < r.t1; t += NT3)
-            part += J.h[0].digstart[(size_t)d * J.h[0].ntile2_max + t];
-        uint64_t tot;
-        block_excl_scan<NT3>(part, s_tmp, &tot);
-        const uint64_t pos = r.pos0 + tot;
-        for (uint32_t i = tid; i < na; i += NT3) sorted_out[pos + i] = s_b[i];
-        return;
-    }
-    if (na > CAP3 || nb > CAP3) {
-        join_fallback(J, s, NS, b, d);
-        return;
-    }
-    sort_slots(kk[1], nb, sh3, s_b, s_bin, s_tmp, false);
-
-    const uint64_t s_lo = LB == 0 ? 0 : ((uint64_t)s << (64 - LB));
-    const uint64_t s_hi = LB == 0 ? ~0ull : (s_lo + ((1ull << (64 - LB)) - 1));
-    const uint64_t t_lo = J.t_lo, t_hi = J.t_hi;
+    SubRef r[2];
+    uint32_t nt[2] = {0, 0};
+    bool huge = false;
 #pragma unroll
-    for (int k = 0; k < KP3; ++k) {
-        const uint32_t q = tid + k * NT3;
-        if (q >= na) continue;
-        const uint64_t a = kk[0][k];
-        const uint64_t wlo = a >= t_hi ? a - t_hi : 0;
-        const uint64_t whi = a <= ~0ull - t_lo ? a + t_lo : ~0ull;
-        const uint64_t clo = wlo > s_lo ? wlo : s_lo;
-        const uint64_t chi = whi < s_hi ? whi : s_hi;
-        const uint32_t b0 = dig(clo, sh3, NB3 - 1), b1 = dig(chi, sh3, NB3 - 1);
-        const uint32_t e = s_bin[b1 + 1];
-        for (uint32_t i = s_bin[b0]; i < e; ++i) {
-            const uint64_t bk = s_b[i];
-            if (bk >= wlo && bk <= whi) emit_pair(J, a, bk);
+    for (int h = 0; h < NH; ++h) {
+        r[h] = sub_ref(J.h[h], b);
+        nt[h] = r[h].t1 - r[h].t0;
+        huge = huge || (J.h[h].bstart[b + 1] - r[h].pos0) >= (1ull << 29);
+    }
+    if (huge) {
+        // 32-bit slot offsets cannot address this bucket
+        if (SORT_OUT) {
+            if (tid == 0) atomicOr(J.flags, 1u);
+        } else {
+            join_fallback(J, s, NS, b, d);
         }
-        // window reaching past this sub-bucket (or wrapping past 0)
-        const bool low_edge = (a - s_lo) < t_hi;
-        const bool high_edge = (s_hi - a) < t_lo;
-        if (low_edge || high_edge) {
-            const uint32_t nlo = (s + NS - 1) & (NS - 1), nhi = (s + 1) & (NS - 1);
-            if (low_edge) edge_scan(J, a, s, nlo, wlo, whi);
-            if (high_edge && !(low_edge && nhi == nlo)) edge_scan(J, a, s, nhi, wlo, whi);
+        return;
+    }
+    // tile `tid`'s segment bounds of each half, loaded up front when the
+    // bucket's tiles fit one gather chunk
+    const bool pre = max(nt[0], NH > 1 ? nt[1] : 0u) <= (uint32_t)MAXT;
+    uint32_t pst[2] = {0, 0}, pen[2] = {0, 0};
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+        const HalfArgs &H = J.h[h];
+        if (pre && (uint32_t)tid < nt[h]) {
+            pst[h] = H.digstart[(size_t)d * H.ntile2_max + r[h].t0 + tid];
+            pen[h] = H.digstart[(size_t)(d + 1) * H.ntile2_max + r[h].t0 + tid];
         }
     }
+    join_sub<SORT_OUT>(J, s, b, d, r, pre, pst, pen, sorted_out, L);
 }
 
 // ------------------------------------------------------------------ K4
@@ -1192,16 +1505,16 @@ hipError_t MultiLaunch::launch(const JobArgs *jobs_dev, const uint32_t *bases_de
 // bits together with its pattern index, then every a probes the bins its
 // cyclic window overlaps and emits pattern pairs directly.  Workgroups are
 // persistent and take the next job (largest first) from an atomic counter.
-__global__ __launch_bounds__(NT3) void k_small(const SmallJob *jobs, int njobs, uint32_t *queue) {
+__global__ __launch_bounds__(NTS) void k_small(const SmallJob *jobs, int njobs, uint32_t *queue) {
     __shared__ uint64_t s_a[1 << SMALL_HALF];
     __shared__ uint64_t s_b[1 << SMALL_HALF];
     __shared__ uint16_t s_bi[1 << SMALL_HALF];
     __shared__ uint32_t s_bin[NB3 + 1];
-    __shared__ uint64_t s_tmp[NT3 / 64 + 2];
+    __shared__ uint64_t s_tmp[NTS / 64 + 2];
     __shared__ int s_job;
     __shared__ unsigned long long s_cnt;
     const int tid = threadIdx.x;
-    constexpr int KPS = (1 << SMALL_HALF) / NT3;
+    constexpr int KPS = (1 << SMALL_HALF) / NTS;
     for (;;) {
         if (tid == 0) s_job = (int)atomicAdd(queue, 1u);
         __syncthreads();
@@ -1210,9 +1523,9 @@ __global__ __launch_bounds__(NT3) void k_small(const SmallJob *jobs, int njobs, 
         const SmallJob &S = jobs[j];
         const int na = S.na, nb = S.nb;
         const uint32_t NA = 1u << na, NBk = 1u << nb;
-        for (int i = tid; i < NB3; i += NT3) s_bin[i] = 0;
+        for (int i = tid; i < NB3; i += NTS) s_bin[i] = 0;
         if (tid == 0) s_cnt = 0;
-        for (uint32_t i = tid; i < NA; i += NT3) {
+        for (uint32_t i = tid; i < NA; i += NTS) {
             uint64_t v = 0;
             for (int e = 0; e < na; ++e)
                 if ((i >> e) & 1) v += S.w[e];
@@ -1223,7 +1536,7 @@ __global__ __launch_bounds__(NT3) void k_small(const SmallJob *jobs, int njobs, 
         uint32_t rk[KPS];
 #pragma unroll
         for (int k = 0; k < KPS; ++k) {
-            const uint32_t i = tid + k * NT3;
+            const uint32_t i = tid + k * NTS;
             if (i < NBk) {
                 uint64_t v = 0;
                 for (int e = 0; e < nb; ++e)
@@ -1233,11 +1546,11 @@ __global__ __launch_bounds__(NT3) void k_small(const SmallJob *jobs, int njobs, 
             }
         }
         __syncthreads();
-        lds_excl_scan<NT3, NB3 / NT3>(s_bin, NB3, s_tmp);
+        lds_excl_scan<NTS, NB3 / NTS>(s_bin, NB3, s_tmp);
         if (tid == 0) s_bin[NB3] = NBk;
 #pragma unroll
         for (int k = 0; k < KPS; ++k) {
-            const uint32_t i = tid + k * NT3;
+            const uint32_t i = tid + k * NTS;
             if (i < NBk) {
                 const uint32_t p = s_bin[(uint32_t)(kb[k] >> (64 - LB3))] + rk[k];
                 s_b[p] = kb[k];
@@ -1246,7 +1559,7 @@ __global__ __launch_bounds__(NT3) void k_small(const SmallJob *jobs, int njobs, 
         }
         __syncthreads();
         const uint64_t t_lo = S.t_lo, t_hi = S.t_hi;
-        for (uint32_t i = tid; i < NA; i += NT3) {
+        for (uint32_t i = tid; i < NA; i += NTS) {
             const uint64_t a = s_a[i];
             // the cyclic window [a - t_hi, a + t_lo] as up to two plain ranges
             uint64_t lo[2], hi[2];
@@ -1296,7 +1609,7 @@ __global__ void k_small_init(uint32_t *queue) {
 hipError_t launch_small(const SmallJob *jobs_dev, int njobs, uint32_t *queue_dev, int grid, hipStream_t st) {
     if (njobs <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_small_init, dim3(1), dim3(64), 0, st, queue_dev);
-    hipLaunchKernelGGL(k_small, dim3(grid), dim3(NT3), 0, st, jobs_dev, njobs, queue_dev);
+    hipLaunchKernelGGL(k_small, dim3(grid), dim3(NTS), 0, st, jobs_dev, njobs, queue_dev);
     return hipGetLastError();
 }
 

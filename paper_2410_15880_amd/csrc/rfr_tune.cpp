@@ -34,9 +34,12 @@ static bool load_table(const char *path) {
         if (line[0] == '#') continue;
         int lg, b1, sub;
         double ms;
-        if (std::sscanf(line, "%d %d %d %lf", &lg, &b1, &sub, &ms) == 4 && lg >= 0 && lg <= dev::MAX_HALF &&
-            b1 >= 0 && b1 <= dev::MAXB1_LOG && (sub == 10 || sub == 11)) {
+        if (std::sscanf(line, "%d %d %d %lf", &lg, &b1, &sub, &ms) != 4 || lg < 0 || lg > dev::MAX_HALF) continue;
+        if (b1 >= 0 && b1 <= dev::MAXB1_LOG && (sub == 10 || sub == 11)) {
             set_tune(lg, Tune{b1, sub, ms});
+            ++loaded;
+        } else if (b1 == -1 && sub == -1) {  // back to the fixed rule
+            set_tune(lg, Tune{-1, -1, 0.0});
             ++loaded;
         }
     }

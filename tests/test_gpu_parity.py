@@ -230,3 +230,46 @@ def test_small_budget_context_streams_half_a(R):
             say("budget seed", w.seed)
             e = g[str(w.seed)]
             assert c.factor(w.coeffs) == (e["content"], [tuple(f) for f in e["factors"]])
+
+
+# ------------------------------------------------------------------ multi-chunk gather
+# A level-1 bucket with more tiles than one gather chunk makes the join stage
+# its sub-buckets' segments in several chunks (and read the segment bounds
+# from global memory instead of preloading them); a tuning table that forces a
+# single level-1 bucket routes mid-size searches there.
+
+
+def _force_tuning(R, tmp_path, lines):
+    p = tmp_path / "tune.txt"
+    p.write_text("".join("%d %d %d 0\n" % l for l in lines))
+    R.load_tuning(str(p))
+
+
+def test_multi_chunk_gather_matches_oracle(R, tmp_path):
+    lgs = [20, 21, 22]
+    try:
+        _force_tuning(R, tmp_path, [(lg, 0, 11) for lg in lgs])
+        for n in (41, 43):
+            rng = random.Random(700 + n)
+            w = planted_weights(rng, n, k_rel=5)
+            say("multi-chunk gather n=%d" % n)
+            assert R.recombine_dev(w, n + 9, 6, cap=1 << 12) == O.search_hs(w, n + 9, 6)
+    finally:
+        _force_tuning(R, tmp_path, [(lg, -1, -1) for lg in lgs])
+
+
+def test_multi_chunk_gather_batched_matches_golden(R, tmp_path):
+    g = json.load(open(os.path.join(HERE, "golden", "golden_batch.json")))["cases"]
+    ws = [w for w in W.config_batch() if str(w.seed) in g]
+    pick = [w for w in ws if 40 <= len(w.coeffs) - 1 <= 80][:48]
+    lgs = list(range(14, 23))
+    try:
+        _force_tuning(R, tmp_path, [(lg, 0, 11) for lg in lgs])
+        with R.Context(0) as c:
+            say("multi-chunk gather batch of %d" % len(pick))
+            got = c.factor_batch([w.coeffs for w in pick])
+        for w, r in zip(pick, got):
+            e = g[str(w.seed)]
+            assert r == (e["content"], [tuple(f) for f in e["factors"]]), w.seed
+    finally:
+        _force_tuning(R, tmp_path, [(lg, -1, -1) for lg in lgs])
