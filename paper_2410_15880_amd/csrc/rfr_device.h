@@ -15,8 +15,8 @@ namespace rfr {
 namespace dev {
 // ---- K0/K1/K4: Gray-code enumeration (256 lanes own the low 8 pattern bits)
 constexpr int NT1 = 256;          // threads per workgroup
-constexpr int KPT1 = 16;          // Gray steps (keys per thread) per LDS tile
-constexpr int T1 = NT1 * KPT1;    // keys per K1 tile (32 KB of LDS)
+constexpr int KPT1 = 32;          // Gray steps (keys per thread) per LDS tile
+constexpr int T1 = NT1 * KPT1;    // keys per K1 tile (64 KB of LDS)
 constexpr int TILES1 = 8;         // tiles per K0/K1 workgroup
 constexpr int MAXB1_LOG = 11;     // level-1 digit bits (buckets) at most
 constexpr int MAXB1 = 1 << MAXB1_LOG;

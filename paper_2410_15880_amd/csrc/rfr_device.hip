@@ -159,13 +159,22 @@ __global__ void k_init(JobArgs Jarg, Multi M) {
 // gray(h) = h ^ (h >> 1), so going from h to h+1 flips exactly bit ctz(h+1) and
 // changes the high sum by one wavefront-uniform +-w.
 template <bool COUNT, int NBMAX, bool MULTI>
-__global__ __launch_bounds__(NT1) void k_enum(JobArgs Jarg, Multi M) {
+__global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(2))) void k_enum(JobArgs Jarg, Multi M) {
     const JobArgs *Jp;
     uint32_t wg;
     if (!pick<MULTI>(Jarg, M, COUNT ? ST_COUNT : ST_ENUM, Jp, wg)) return;
     const JobArgs &J = *Jp;
     const HalfArgs &H = J.h[blockIdx.y];
     if (wg >= H.nwg1) return;
+    // Workgroup w's keys of bucket b fill the range between w - 1's and
+    // w + 1's, so the cache lines at those seams are shared.  Neighbouring
+    // workgroups run on the same XCD (hardware deals workgroups out to the 8
+    // XCDs in turn), and odd workgroups fill their ranges from the top down, so
+    // both halves of a seam line are written at about the same time (in both
+    // workgroups' first tile, or both their last) into the same L2 instead of
+    // reaching memory as two partial writes.
+    if (!COUNT && !MULTI && (H.nwg1 & 7) == 0 && H.nwg1 >= 64) wg = (wg & 7) * (H.nwg1 >> 3) + (wg >> 3);
+    const bool back = !COUNT && (wg & 1);
     const int B1 = J.B1;
     const int nb = 1 << B1;
     const int sh1 = 64 - B1;
@@ -184,8 +193,14 @@ __global__ __launch_bounds__(NT1) void k_enum(JobArgs Jarg, Multi M) {
     if (tid < H.m) s_w[tid] = J.wts[blockIdx.y][tid];
     for (int b = tid; b < nb; b += NT1) {
         s_cnt[b] = 0;
-        if (!COUNT) s_cur[b] = H.bstart[b] + H.hist1[(size_t)b * H.nwg1 + wg];
+        if (!COUNT) {
+            // range of (b, wg): [bstart + prefix(wg), bstart + prefix(wg + 1))
+            const uint64_t lo = H.hist1[(size_t)b * H.nwg1 + wg];
+            const uint64_t hi = wg + 1 < H.nwg1 ? H.hist1[(size_t)b * H.nwg1 + wg + 1] : H.bstart[b + 1] - H.bstart[b];
+            s_cur[b] = H.bstart[b] + (back ? hi : lo);
+        }
     }
+    uint64_t *const keys_out = H.keys;
     __syncthreads();
 
     uint64_t slo = J.kbase[blockIdx.y];
@@ -197,6 +212,15 @@ __global__ __launch_bounds__(NT1) void k_enum(JobArgs Jarg, Multi M) {
     uint64_t shi = 0;
     for (int i = 0; i < H.m - H.L; ++i)
         if ((g >> i) & 1) shi += s_w[H.L + i];
+    // Tiles start at multiples of KPT1 steps, so inside a tile step k + 1 flips
+    // bit ctz(k + 1) < log2 KPT1: those weights sit in registers and only the
+    // step into the next tile reads its weight by a computed index.
+    constexpr int LOGK = __builtin_ctz(KPT1);
+    static_assert((1 << LOGK) == KPT1, "tiles of a power-of-two number of Gray steps");
+    const int mh = H.m - H.L;
+    uint64_t wlow[LOGK];
+#pragma unroll
+    for (int i = 0; i < LOGK; ++i) wlow[i] = mh > i ? s_w[H.L + i] : 0;
 
     for (uint64_t h = h0; h < h1; h += KPT1) {
         const int ns = (int)min((uint64_t)KPT1, h1 - h);
@@ -206,9 +230,9 @@ __global__ __launch_bounds__(NT1) void k_enum(JobArgs Jarg, Multi M) {
             key[k] = slo + shi;
             const uint64_t t = h + k + 1;
             if (k < ns && t < h1) {
-                const int b = __builtin_ctzll(t);
+                const int b = k < KPT1 - 1 ? __builtin_ctz(k + 1) : __builtin_ctzll(t);
+                const uint64_t wb = k < KPT1 - 1 ? wlow[__builtin_ctz(k + 1) % LOGK] : s_w[H.L + b];
                 g ^= 1ull << b;
-                const uint64_t wb = s_w[H.L + b];
                 shi += ((g >> b) & 1) ? wb : (0 - wb);
             }
         }
@@ -240,16 +264,29 @@ __global__ __launch_bounds__(NT1) void k_enum(JobArgs Jarg, Multi M) {
                 const uint32_t d = dig(key[k], sh1, m1);
                 s_buf[s_off[d] + rank[k]] = key[k];
             }
+        // destination of tile slot p of bucket d: s_cur[d] - s_off[d] + p, the
+        // cursor first stepping down by the run length when filling downwards
+        for (int b = tid; b < nb; b += NT1) s_cur[b] -= s_off[b] + (back ? s_cnt[b] : 0u);
         __syncthreads();
         const int tile = ns * nl;
-        for (int p = tid; p < tile; p += NT1) {
-            const uint64_t kk = s_buf[p];
-            const uint32_t d = dig(kk, sh1, m1);
-            H.keys[s_cur[d] + (uint64_t)(p - (int)s_off[d])] = kk;
+        // in groups of 8 slots: LDS reads first (slots past the tile read stale
+        // data and store nothing), then the stores; `keys_out` is a local so
+        // that the stores do not make the compiler reload it from the argument
+        // block between them
+#pragma unroll
+        for (int i0 = 0; i0 < KPT1; i0 += 8) {
+            uint64_t kv[8], dst[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) kv[i] = s_buf[tid + (i0 + i) * NT1];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) dst[i] = s_cur[dig(kv[i], sh1, m1)] + (uint64_t)(tid + (i0 + i) * NT1);
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (tid + (i0 + i) * NT1 < tile) keys_out[dst[i]] = kv[i];
         }
         __syncthreads();
         for (int b = tid; b < nb; b += NT1) {
-            s_cur[b] += s_cnt[b];
+            s_cur[b] += s_off[b] + (back ? 0u : s_cnt[b]);
             s_cnt[b] = 0;
         }
         __syncthreads();
@@ -355,6 +392,7 @@ __global__ __launch_bounds__(NT2) void k_tile2(JobArgs Jarg, Multi M) {
     const int b = s_b;
     const uint64_t base = H.bstart[b] + (uint64_t)(tile - H.tstart[b]) * T2;
     const int len = (int)min((uint64_t)T2, H.bstart[b + 1] - base);
+    uint64_t *const keys = H.keys + base;  // a local: stores must not force reloads of the argument block
 
     uint64_t key[KPT2];
     uint32_t rank[KPT2];
@@ -362,7 +400,7 @@ __global__ __launch_bounds__(NT2) void k_tile2(JobArgs Jarg, Multi M) {
 #pragma unroll
     for (int k = 0; k < KPT2; ++k) {
         const int p = tid + k * NT2;
-        if (p < len) key[k] = __builtin_nontemporal_load(&H.keys[base + p]);
+        if (p < len) key[k] = __builtin_nontemporal_load(&keys[p]);
     }
 #pragma unroll
     for (int k = 0; k < KPT2; ++k) {
@@ -379,7 +417,12 @@ __global__ __launch_bounds__(NT2) void k_tile2(JobArgs Jarg, Multi M) {
         if (p < len) s_buf[s_off[dig(key[k], sh2, m2)] + rank[k]] = key[k];
     }
     __syncthreads();
-    for (int p = tid; p < len; p += NT2) H.keys[base + p] = s_buf[p];
+    uint64_t kv[KPT2];
+#pragma unroll
+    for (int k = 0; k < KPT2; ++k) kv[k] = s_buf[tid + k * NT2];
+#pragma unroll
+    for (int k = 0; k < KPT2; ++k)
+        if (tid + k * NT2 < len) keys[tid + k * NT2] = kv[k];
     for (int d = tid; d < nd; d += NT2) H.digstart[(size_t)d * H.ntile2_max + tile] = (uint16_t)s_off[d];
     if (tid == 0) H.digstart[(size_t)nd * H.ntile2_max + tile] = (uint16_t)len;
 }
