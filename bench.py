@@ -36,7 +36,9 @@ STAGE_KERNEL = {"count": "k_enum<true>", "scan": "k_scan_cols+k_scan_buckets",
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_search_kernels_degree100x16.txt")
+# the kernels and the radix-split table the library loads at context creation
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2410_15880_amd", "csrc", f) for f in ("rfr_device.hip", "rfr_device.h")]
+KERNEL_SOURCES.append(os.path.join(ROOT, "paper_2410_15880_amd", "tuning", "mi355x.txt"))
 
 
 def kernel_source_hash():

@@ -245,6 +245,13 @@ def _force_tuning(R, tmp_path, lines):
     R.load_tuning(str(p))
 
 
+def _restore_tuning(R, tmp_path, lgs):
+    # back to the fixed rule, then to the shipped table if there is one
+    _force_tuning(R, tmp_path, [(lg, -1, -1) for lg in lgs])
+    if os.path.exists(R.TUNING_PATH):
+        R.load_tuning(R.TUNING_PATH)
+
+
 def test_multi_chunk_gather_matches_oracle(R, tmp_path):
     lgs = [20, 21, 22]
     try:
@@ -255,7 +262,7 @@ def test_multi_chunk_gather_matches_oracle(R, tmp_path):
             say("multi-chunk gather n=%d" % n)
             assert R.recombine_dev(w, n + 9, 6, cap=1 << 12) == O.search_hs(w, n + 9, 6)
     finally:
-        _force_tuning(R, tmp_path, [(lg, -1, -1) for lg in lgs])
+        _restore_tuning(R, tmp_path, lgs)
 
 
 def test_multi_chunk_gather_batched_matches_golden(R, tmp_path):
@@ -272,4 +279,4 @@ def test_multi_chunk_gather_batched_matches_golden(R, tmp_path):
             e = g[str(w.seed)]
             assert r == (e["content"], [tuple(f) for f in e["factors"]]), w.seed
     finally:
-        _force_tuning(R, tmp_path, [(lg, -1, -1) for lg in lgs])
+        _restore_tuning(R, tmp_path, lgs)
