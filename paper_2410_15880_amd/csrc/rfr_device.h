@@ -28,8 +28,9 @@ constexpr int MAXB2_LOG = 12;
 constexpr int MAXB2 = 1 << MAXB2_LOG;
 // ---- K3: sub-bucket gather, LDS radix sort of B', band join probing it with A
 constexpr int NT3 = 256;
-constexpr int SUB_LOG = 11;       // mean keys of the larger half per sub-bucket = 2^SUB_LOG
-constexpr int KP3 = 12;           // key slots per thread per half (registers)
+constexpr int SUB_LOG = 10;       // mean keys of the larger half per sub-bucket = 2^SUB_LOG (at most)
+constexpr int SUB_LOG_MIN = 9;    // smallest sub-bucket mean the tuner may choose
+constexpr int KP3 = 8;            // key slots per thread per half (registers)
 constexpr int CAP3 = NT3 * KP3;   // keys per half a sub-bucket may hold on the fast path
 constexpr int LB3 = 10;           // bits of the in-LDS counting sort of B'
 constexpr int NB3 = 1 << LB3;
@@ -141,7 +142,7 @@ struct SmallJob {
 // Autotuned digit split for one size class (log2 of the larger half).
 struct Tune {
     int b1;       // level-1 digit bits (-1: default)
-    int sub_log;  // log2 of the mean keys per sub-bucket (10 or 11; -1: default)
+    int sub_log;  // log2 of the mean keys per sub-bucket (SUB_LOG_MIN..SUB_LOG; -1: default)
     double ms;    // time measured by the autotuner
 };
 void set_tune(int lg, Tune t);

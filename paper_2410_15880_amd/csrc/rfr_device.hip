@@ -511,7 +511,8 @@ __device__ __forceinline__ uint64_t block_excl_max2(uint64_t v, uint64_t *s_tmp)
 // gives the segments' key offsets.  The tile map q -> tile is built in LDS
 // without walking the segments: each non-empty segment puts its tile number at
 // its first offset, and a prefix maximum over the map (tiles come in offset
-// order) fills the rest; every thread owns 12 consecutive map bytes per half.
+// order) fills the rest; every thread owns CAP3 / NT3 consecutive map bytes per
+// half.
 // Each tile's key offset from the bucket start minus its first slot goes to
 // LDS, so a slot's address is one LDS read and an add, and all slot loads of a
 // chunk are in flight together.  Buckets below 2^29 keys keep byte offsets in
@@ -522,8 +523,9 @@ __device__ __forceinline__ void gather_regs(const JobArgs &J, int d, const SubRe
                                             const uint32_t (&pst)[2], const uint32_t (&pen)[2],
                                             uint64_t (&kk)[2][KP3], uint32_t (&n)[2], uint32_t (*s_src)[MAXT],
                                             uint32_t *s_mapw, uint64_t *s_tmp) {
-    static_assert(CAP3 == NT3 * 12, "the map scan gives every thread 12 bytes per half");
-    constexpr int MW = CAP3 / 4;  // map words per half
+    constexpr int MW = CAP3 / 4;     // map words per half
+    constexpr int TW = MW / NT3;     // map words each thread owns per half
+    static_assert(TW * NT3 * 4 == CAP3, "every thread owns whole map words");
     const int tid = threadIdx.x;
     uint8_t *s_map = (uint8_t *)s_mapw;
     uint32_t nt[2] = {0, 0};
@@ -561,14 +563,14 @@ __device__ __forceinline__ void gather_regs(const JobArgs &J, int d, const SubRe
         }
         __syncthreads();
         // prefix maximum over the map
-        uint32_t w[2][3];
+        uint32_t w[2][TW];
         uint64_t mx = 0;
 #pragma unroll
         for (int h = 0; h < NH; ++h) {
             uint32_t m = 0;
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                w[h][j] = s_mapw[h * MW + tid * 3 + j];
+            for (int j = 0; j < TW; ++j) {
+                w[h][j] = s_mapw[h * MW + tid * TW + j];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) m = max(m, (w[h][j] >> (8 * k)) & 0xFFu);
             }
@@ -579,14 +581,14 @@ __device__ __forceinline__ void gather_regs(const JobArgs &J, int d, const SubRe
         for (int h = 0; h < NH; ++h) {
             uint32_t m = (uint32_t)(px >> (32 * h));
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
+            for (int j = 0; j < TW; ++j) {
                 uint32_t o = 0;
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     m = max(m, (w[h][j] >> (8 * k)) & 0xFFu);
                     o |= m << (8 * k);
                 }
-                s_mapw[h * MW + tid * 3 + j] = o;
+                s_mapw[h * MW + tid * TW + j] = o;
             }
         }
         __syncthreads();
@@ -822,14 +824,35 @@ __device__ __forceinline__ void join_semi(const JobArgs &J, uint32_t s, int b, i
         for (int k = 0; k < KP3; ++k)
             if (tid + k * NT3 < nb) mark1(bm, dig(kk[1][k], shc, NC - 1));
         __syncthreads();
-        // A keys whose window meets a marked cell
-        uint32_t hits = 0;
+        // A keys whose window meets a marked cell.  Every slot's own-cell word
+        // is read first with no branch (the reads overlap; an unused slot reads
+        // a stale but in-range cell), the bit tests follow; the rare keys within
+        // a window of their cell's edge take a second pass for the neighbour.
+        uint32_t hits = 0, edge = 0;
+        {
+            uint32_t cl[KP3], wd[KP3];
 #pragma unroll
-        for (int k = 0; k < KP3; ++k) {
-            if (tid + k * NT3 >= na) continue;
-            bool lo, hi;
-            cell_edges(kk[0][k], shc, t_lo, t_hi, lo, hi);
-            if (window_hits<NC>(bm, dig(kk[0][k], shc, NC - 1), lo, hi)) hits |= 1u << k;
+            for (int k = 0; k < KP3; ++k) cl[k] = dig(kk[0][k], shc, NC - 1);
+#pragma unroll
+            for (int k = 0; k < KP3; ++k) wd[k] = bm[cl[k] >> 5];
+            const uint64_t om = (1ull << shc) - 1;
+#pragma unroll
+            for (int k = 0; k < KP3; ++k) {
+                const bool live = tid + k * NT3 < na;
+                const uint64_t off = kk[0][k] & om;
+                hits |= (uint32_t)(live && ((wd[k] >> (cl[k] & 31)) & 1u)) << k;
+                edge |= (uint32_t)(live && (off < t_hi || om - off < t_lo)) << k;
+            }
+            edge &= ~hits;
+        }
+        if (edge) {
+#pragma unroll
+            for (int k = 0; k < KP3; ++k) {  // static slot indices keep kk in registers
+                if (!((edge >> k) & 1u)) continue;
+                bool lo, hi;
+                cell_edges(kk[0][k], shc, t_lo, t_hi, lo, hi);
+                if (window_hits<NC>(bm, dig(kk[0][k], shc, NC - 1), lo, hi)) hits |= 1u << k;
+            }
         }
         uint32_t o = wave_append(&L.nl[0], __popc(hits));
 #pragma unroll
@@ -850,10 +873,14 @@ __device__ __forceinline__ void join_semi(const JobArgs &J, uint32_t s, int b, i
                 mark_window<NC>(bm, dig(LA[i], shc, NC - 1), lo, hi);
             }
             __syncthreads();
-            uint32_t bh = 0;
+            uint32_t bh = 0, cl[KP3], wd[KP3];
+#pragma unroll
+            for (int k = 0; k < KP3; ++k) cl[k] = dig(kk[1][k], shc, NC - 1);
+#pragma unroll
+            for (int k = 0; k < KP3; ++k) wd[k] = bm[cl[k] >> 5];
 #pragma unroll
             for (int k = 0; k < KP3; ++k)
-                if (tid + k * NT3 < nb && bit(bm, dig(kk[1][k], shc, NC - 1))) bh |= 1u << k;
+                bh |= (uint32_t)(tid + k * NT3 < nb && ((wd[k] >> (cl[k] & 31)) & 1u)) << k;
             uint32_t ob = wave_append(&L.nl[1], __popc(bh));
 #pragma unroll
             for (int k = 0; k < KP3; ++k)
@@ -965,7 +992,7 @@ __device__ __forceinline__ void join_sub(const JobArgs &J, uint32_t s, int b, in
 //     the neighbour sub-bucket of B' from global memory (edge_scan).
 // With SORT_OUT the single half is fully sorted in LDS and written instead.
 template <bool SORT_OUT, bool MULTI>
-__global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k_join(JobArgs Jarg, Multi M,
+__global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(5))) void k_join(JobArgs Jarg, Multi M,
                                                                                         uint64_t *sorted_out) {
     constexpr int NH = SORT_OUT ? 1 : 2;
     const JobArgs *Jp;
@@ -1251,7 +1278,7 @@ static void plan_bits(uint64_t nmax, int &B1, int &B2) {
     int lg = 0;
     while ((1ull << lg) < nmax) ++lg;
     const Tune tn = get_tune(lg);
-    const int sub = (tn.sub_log == 10 || tn.sub_log == 11) ? tn.sub_log : SUB_LOG;
+    const int sub = (tn.sub_log >= SUB_LOG_MIN && tn.sub_log <= SUB_LOG) ? tn.sub_log : SUB_LOG;
     int LB = lg > sub ? lg - sub : 0;
     if (LB > MAXB1_LOG + MAXB2_LOG) LB = MAXB1_LOG + MAXB2_LOG;
     if (tn.b1 >= 0) {

@@ -2,7 +2,7 @@
 //
 // For each size class (log2 of the larger half's key count) the tuner times
 // the full device search on seeded random weights for every candidate split:
-// the sub-bucket size (mean 2^10 or 2^11 keys of the larger half) and the
+// the sub-bucket size (mean 2^9 or 2^10 keys of the larger half) and the
 // number of level-1 bits (the rest go to the level-2 tile sort).  The fastest
 // split of each class is installed for the process and written to a text
 // table, which contexts load at creation (see tuning_autoload).
@@ -35,7 +35,7 @@ static bool load_table(const char *path) {
         int lg, b1, sub;
         double ms;
         if (std::sscanf(line, "%d %d %d %lf", &lg, &b1, &sub, &ms) != 4 || lg < 0 || lg > dev::MAX_HALF) continue;
-        if (b1 >= 0 && b1 <= dev::MAXB1_LOG && (sub == 10 || sub == 11)) {
+        if (b1 >= 0 && b1 <= dev::MAXB1_LOG && sub >= dev::SUB_LOG_MIN && sub <= dev::SUB_LOG) {
             set_tune(lg, Tune{b1, sub, ms});
             ++loaded;
         } else if (b1 == -1 && sub == -1) {  // back to the fixed rule
@@ -95,7 +95,7 @@ extern "C" rfr_status rfr_autotune(rfr_ctx *ctx, int lg_lo, int lg_hi, const cha
         std::vector<uint64_t> w(n);
         for (auto &x : w) x = splitmix64(seed);
         Tune best{-1, -1, 1e30};
-        for (int sub : {10, 11}) {
+        for (int sub = dev::SUB_LOG_MIN; sub <= dev::SUB_LOG; ++sub) {
             const int LB = lg > sub ? lg - sub : 0;
             // level-1 buckets much larger than the level-2 digit range only
             // add tiles per sub-bucket, so the sweep starts near an even split

@@ -255,7 +255,7 @@ def _restore_tuning(R, tmp_path, lgs):
 def test_multi_chunk_gather_matches_oracle(R, tmp_path):
     lgs = [20, 21, 22]
     try:
-        _force_tuning(R, tmp_path, [(lg, 0, 11) for lg in lgs])
+        _force_tuning(R, tmp_path, [(lg, 0, 10) for lg in lgs])
         for n in (41, 43):
             rng = random.Random(700 + n)
             w = planted_weights(rng, n, k_rel=5)
@@ -271,7 +271,7 @@ def test_multi_chunk_gather_batched_matches_golden(R, tmp_path):
     pick = [w for w in ws if 40 <= len(w.coeffs) - 1 <= 80][:48]
     lgs = list(range(14, 23))
     try:
-        _force_tuning(R, tmp_path, [(lg, 0, 11) for lg in lgs])
+        _force_tuning(R, tmp_path, [(lg, 0, 10) for lg in lgs])
         with R.Context(0) as c:
             say("multi-chunk gather batch of %d" % len(pick))
             got = c.factor_batch([w.coeffs for w in pick])
