@@ -189,6 +189,20 @@ const char *rfr_last_error(void);
 rfr_status rfr_weights(const int64_t *coeffs, int degree, uint64_t *w_out, int32_t *n_out,
                        int32_t *n_real_out, uint64_t *t_lo, uint64_t *t_hi);
 
+/* The host stages of rfr_factor_batch for `count` polynomials (same packing
+ * as rfr_factor_batch): normalisation on the host, the roots of every
+ * polynomial of degree >= 2 on the device (one workgroup per polynomial:
+ * FP64 Aberth, double-double Newton polish, inclusion radii; Section 2, Eq 1),
+ * then the disc checks, elements, weights and window (Section 3.3, Eq 18-19)
+ * on the host, which finds the roots itself for a polynomial whose device
+ * roots fail a check.  Per polynomial i: w_out[off_i .. off_i + n_i) with
+ * off_i = sum of degrees[j] for j < i (room for degree weights each), n_out,
+ * t_lo, t_hi, device_roots_out (1 if the device roots were used) and
+ * status[i].  Returns RFR_OK unless the arguments or the device fail. */
+rfr_status rfr_prepare_batch(rfr_ctx *ctx, int count, const int64_t *coeffs, const int32_t *degrees,
+                             uint64_t *w_out, int32_t *n_out, uint64_t *t_lo, uint64_t *t_hi,
+                             int32_t *device_roots_out, rfr_status *status);
+
 /* ------------------------------------------------------------------ kernel level */
 
 /* Device workspace for rfr_recombine_dev to search n elements in one pass. */

@@ -28,7 +28,7 @@ EXPORTS = [
     "rfr_strerror", "rfr_last_error", "rfr_weights", "rfr_recombine_workspace_bytes",
     "rfr_recombine_dev", "rfr_expand_workspace_bytes", "rfr_expand_dev",
     "rfr_profile", "rfr_profile_read", "rfr_recombine_min_workspace_bytes",
-    "rfr_autotune", "rfr_load_tuning",
+    "rfr_autotune", "rfr_load_tuning", "rfr_prepare_batch",
 ]
 
 
@@ -94,6 +94,9 @@ def lib():
         "rfr_expand_dev": ([C.POINTER(u64), C.c_int, C.c_int, P, sz, P, P], C.c_int),
         "rfr_profile": ([P, C.c_int], C.c_int),
         "rfr_autotune": ([P, C.c_int, C.c_int, C.c_char_p], C.c_int),
+        "rfr_prepare_batch": ([P, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(u64),
+                               C.POINTER(C.c_int32), C.POINTER(u64), C.POINTER(u64), C.POINTER(C.c_int32),
+                               C.POINTER(C.c_int)], C.c_int),
         "rfr_load_tuning": ([C.c_char_p], C.c_int),
         "rfr_profile_read": ([P, C.POINTER(Profile)], C.c_int),
     }
@@ -199,6 +202,29 @@ class Context:
             else:
                 res.append(RFRError(sts[i], "batch entry %d" % i))
         return res
+
+    def prepare_batch(self, polys: Sequence[Sequence[int]]) -> List:
+        """Host stages of the batched path with device roots: per polynomial a
+        dict (w, n, t_lo, t_hi, device_roots) or an RFRError."""
+        n = len(polys)
+        flat = [int(c) for p in polys for c in p]
+        degs = [len(p) - 1 for p in polys]
+        w = (C.c_uint64 * max(sum(degs), 1))()
+        nn = (C.c_int32 * n)()
+        tlo = (C.c_uint64 * n)()
+        thi = (C.c_uint64 * n)()
+        dr = (C.c_int32 * n)()
+        sts = (C.c_int * n)()
+        _check(lib().rfr_prepare_batch(self._h, n, _i64(flat), (C.c_int32 * n)(*degs), w, nn, tlo, thi, dr, sts))
+        out, off = [], 0
+        for i in range(n):
+            if sts[i] == RFR_OK:
+                out.append({"w": [int(w[off + k]) for k in range(nn[i])], "n": nn[i], "t_lo": tlo[i],
+                            "t_hi": thi[i], "device_roots": bool(dr[i])})
+            else:
+                out.append(RFRError(sts[i], "batch entry %d" % i))
+            off += degs[i]
+        return out
 
     # ---- tuning
     def autotune(self, lg_lo: int = 12, lg_hi: int = 27, path: Optional[str] = None):

@@ -35,6 +35,7 @@ GXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-I" + INC, "-I"
 
 UNITS = [
     ("rfr_device.hip", "hip"),
+    ("rfr_roots.hip", "hipexact"),
     ("rfr_host.cpp", "gxx"),
     ("rfr_abi.cpp", "hiphost"),
     ("rfr_batch.cpp", "hip"),
@@ -47,6 +48,8 @@ def _cmd(src: str, kind: str, obj: str):
     path = os.path.join(CSRC, src)
     if kind == "hip":
         return [HIPCC] + HIP_FLAGS + ["-c", path, "-o", obj]
+    if kind == "hipexact":  # double-double arithmetic: no contraction
+        return [HIPCC] + HIP_FLAGS + ["-ffp-contract=off", "-c", path, "-o", obj]
     if kind == "hiphost":
         return [HIPCC] + HOST_HIP_FLAGS + ["-c", path, "-o", obj]
     return ["g++"] + GXX_FLAGS + ["-c", path, "-o", obj]

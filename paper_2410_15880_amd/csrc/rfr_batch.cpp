@@ -1,6 +1,9 @@
 // Batched factorisation: many polynomials of uneven degree in one device pass.
 //
-//  1. host roots / weights / window for every polynomial on a thread pool;
+//  1. normalisation on the host; the roots of every polynomial of degree >= 2
+//     in one device launch (a workgroup per polynomial); disc checks,
+//     elements, weights and window on a thread pool (a polynomial whose device
+//     roots fail the checks has its roots found again on the host);
 //  2. the searches are split by size: small ones (both halves <= 2^SMALL_HALF
 //     keys) go to one persistent kernel (a workgroup per polynomial, largest
 //     first from an atomic queue, everything in LDS); larger ones run through
@@ -18,6 +21,7 @@
 #include <thread>
 
 #include "rfr_ctx.h"
+#include "rfr_roots.h"
 
 namespace rfr {
 
@@ -39,6 +43,10 @@ struct BatchState {
     size_t outd_bytes = 0;
     char *hsum = nullptr;      // pinned: summary copy
     size_t hsum_bytes = 0;
+    char *rdev = nullptr;      // device: root-finder coefficients, jobs and records
+    size_t rdev_bytes = 0;
+    char *rhost = nullptr;     // pinned: the same, staged
+    size_t rhost_bytes = 0;
     std::string sig;           // shape of the captured graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -62,6 +70,8 @@ void batch_release(rfr_ctx *ctx) {
     if (b->host) (void)hipHostFree(b->host);
     if (b->outd) (void)hipFree(b->outd);
     if (b->hsum) (void)hipHostFree(b->hsum);
+    if (b->rdev) (void)hipFree(b->rdev);
+    if (b->rhost) (void)hipHostFree(b->rhost);
     if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->join) (void)hipEventDestroy(b->join);
     if (b->side) (void)hipStreamDestroy(b->side);
@@ -83,6 +93,79 @@ static rfr_status grow(char **p, size_t *have, size_t need, bool pinned, BatchSt
     }
     *have = sz;
     return RFR_OK;
+}
+
+// Buffers outside the captured graph: reallocated without dropping it.
+static rfr_status grow_buf(char **p, size_t *have, size_t need, bool pinned) {
+    if (*have >= need) return RFR_OK;
+    if (*p) (void)(pinned ? hipHostFree(*p) : hipFree(*p));
+    *p = nullptr;
+    *have = 0;
+    size_t sz = need + need / 4;
+    hipError_t e = pinned ? hipHostMalloc((void **)p, sz, hipHostMallocDefault) : hipMalloc((void **)p, sz);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(RFR_ENOMEM, "batch buffer allocation failed");
+    }
+    *have = sz;
+    return RFR_OK;
+}
+
+// Roots of every normalised polynomial of degree >= 2 on the device; rec[i]
+// points at polynomial i's records in host memory (nullptr: none).
+static rfr_status device_roots(BatchState *B, hipStream_t st, std::vector<Prepared> &P,
+                               const std::vector<rfr_status> &status, std::vector<const RootOut *> &rec) {
+    const int count = (int)P.size();
+    rec.assign(count, nullptr);
+    std::vector<int> jobs;
+    std::vector<size_t> co(count, 0), ro(count, 0);
+    size_t nco = 0, nro = 0;
+    for (int i = 0; i < count; ++i) {
+        const int d = (int)P[i].prim.size() - 1;
+        if (status[i] != RFR_OK || d < 2) continue;
+        jobs.push_back(i);
+        co[i] = nco;
+        ro[i] = nro;
+        nco += (size_t)d + 1;
+        nro += (size_t)d;
+    }
+    if (jobs.empty()) return RFR_OK;
+    // layout (same in both buffers): coefficients | jobs | records
+    const size_t o_jobs = (nco * 8 + 255) & ~(size_t)255;
+    const size_t o_out = (o_jobs + jobs.size() * sizeof(RootJob) + 255) & ~(size_t)255;
+    const size_t bytes = o_out + nro * sizeof(RootOut);
+    rfr_status e = grow_buf(&B->rdev, &B->rdev_bytes, bytes, false);
+    if (e == RFR_OK) e = grow_buf(&B->rhost, &B->rhost_bytes, bytes, true);
+    if (e != RFR_OK) return e;
+    int64_t *hc = (int64_t *)B->rhost;
+    RootJob *hj = (RootJob *)(B->rhost + o_jobs);
+    for (size_t k = 0; k < jobs.size(); ++k) {
+        const int i = jobs[k];
+        std::memcpy(hc + co[i], P[i].prim.data(), P[i].prim.size() * 8);
+        hj[k] = RootJob{(const int64_t *)(B->rdev) + co[i], (int)P[i].prim.size() - 1,
+                        (RootOut *)(B->rdev + o_out) + ro[i]};
+    }
+    bool ok = hipMemcpyAsync(B->rdev, B->rhost, o_out, hipMemcpyHostToDevice, st) == hipSuccess;
+    ok = ok && launch_roots((const RootJob *)(B->rdev + o_jobs), (int)jobs.size(), st) == hipSuccess;
+    ok = ok && hipMemcpyAsync(B->rhost + o_out, B->rdev + o_out, nro * sizeof(RootOut), hipMemcpyDeviceToHost,
+                              st) == hipSuccess;
+    ok = ok && hipStreamSynchronize(st) == hipSuccess;
+    if (!ok) return fail(RFR_EDEVICE, "device root finding failed");
+    for (int i : jobs) rec[i] = (const RootOut *)(B->rhost + o_out) + ro[i];
+    return RFR_OK;
+}
+
+// Elements, weights and window of one normalised polynomial from its device
+// root records, or from roots found on the host when there are none or they
+// fail the disc checks.  Returns whether the device roots were used.
+static bool finish_or_host(Prepared &P, const RootOut *rec, rfr_status &st, std::string &err) {
+    if (rec && finish_elements(P, rec, err) == RFR_OK) {
+        st = RFR_OK;
+        return true;
+    }
+    err.clear();
+    st = prepare_elements(P, err);
+    return false;
 }
 
 // Copy each job's count and first HEAD pattern pairs into one compact summary.
@@ -200,11 +283,18 @@ extern "C" rfr_status rfr_factor_batch(rfr_ctx *ctx, int count, const int64_t *c
     uint64_t *sum_d = (uint64_t *)(B->outd + o_sum);
     uint64_t *sum_h = (uint64_t *)B->hsum;
 
-    // ---- 1. host stage on the pool, largest first; the device thread below
-    //         consumes the results as they become ready
+    // ---- 1. normalisation, device roots, then the host stage on the pool,
+    //         largest first; the device thread below consumes the results as
+    //         they become ready
     std::vector<Prepared> P(count);
     std::vector<rfr_status> st(count, RFR_OK);
     std::vector<std::string> err(count);
+    for (int i = 0; i < count; ++i) {
+        st[i] = normalise(coeffs + off[i], degrees[i], P[i], err[i]);
+    }
+    std::vector<const RootOut *> rec;
+    rfr_status rst = device_roots(B, S0, P, st, rec);
+    if (rst != RFR_OK) return rst;
     std::vector<int> order(count), slot(count);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return degrees[a] > degrees[b]; });
@@ -217,7 +307,7 @@ extern "C" rfr_status rfr_factor_batch(rfr_ctx *ctx, int count, const int64_t *c
         pool.emplace_back([&] {
             for (int k; (k = next.fetch_add(1)) < count;) {
                 const int i = order[k];
-                st[i] = prepare(coeffs + off[i], degrees[i], P[i], err[i]);
+                if (st[i] == RFR_OK) (void)finish_or_host(P[i], rec[i], st[i], err[i]);
                 ready[i].store(1, std::memory_order_release);
             }
         });
@@ -451,5 +541,51 @@ extern "C" rfr_status rfr_profile_read(rfr_ctx *ctx, rfr_profile_t *out) {
     *out = ctx->prof;
     out->graph_captures = ctx->batch ? ctx->batch->captures : 0;
     out->graph_replays = ctx->batch ? ctx->batch->replays : 0;
+    return RFR_OK;
+}
+
+extern "C" rfr_status rfr_prepare_batch(rfr_ctx *ctx, int count, const int64_t *coeffs, const int32_t *degrees,
+                                        uint64_t *w_out, int32_t *n_out, uint64_t *t_lo, uint64_t *t_hi,
+                                        int32_t *device_roots_out, rfr_status *status) {
+    if (!ctx || count < 0 ||
+        (count > 0 && (!coeffs || !degrees || !w_out || !n_out || !t_lo || !t_hi || !device_roots_out || !status)))
+        return fail(RFR_EINVAL, "bad batch arguments");
+    if (count == 0) return RFR_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(RFR_EDEVICE, "hipSetDevice failed");
+    std::vector<size_t> off(count + 1, 0);
+    for (int i = 0; i < count; ++i) {
+        if (degrees[i] < 1 || degrees[i] > RFR_MAX_DEGREE) return fail(RFR_EINVAL, "degree out of range");
+        off[i + 1] = off[i] + (size_t)degrees[i] + 1;
+    }
+    if (!ctx->batch) {
+        BatchState *b = new BatchState();
+        if (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess) {
+            ctx->batch = b;
+            batch_release(ctx);
+            return fail(RFR_EDEVICE, "batch stream/event creation failed");
+        }
+        ctx->batch = b;
+    }
+    std::vector<Prepared> P(count);
+    std::vector<rfr_status> st(count, RFR_OK);
+    std::vector<std::string> err(count);
+    for (int i = 0; i < count; ++i) st[i] = normalise(coeffs + off[i], degrees[i], P[i], err[i]);
+    std::vector<const RootOut *> rec;
+    rfr_status e = device_roots(ctx->batch, ctx->main.stream, P, st, rec);
+    if (e != RFR_OK) return e;
+    for (int i = 0; i < count; ++i) {
+        device_roots_out[i] = 0;
+        n_out[i] = 0;
+        t_lo[i] = t_hi[i] = 0;
+        if (st[i] == RFR_OK) device_roots_out[i] = finish_or_host(P[i], rec[i], st[i], err[i]) ? 1 : 0;
+        status[i] = st[i];
+        if (st[i] != RFR_OK) continue;
+        n_out[i] = P[i].n;
+        t_lo[i] = P[i].t_lo;
+        t_hi[i] = P[i].t_hi;
+        std::memcpy(w_out + off[i] - i, P[i].w.data(), P[i].w.size() * 8);
+    }
     return RFR_OK;
 }

@@ -34,7 +34,7 @@ constexpr int KP3 = 8;            // key slots per thread per half (registers)
 constexpr int CAP3 = NT3 * KP3;   // keys per half a sub-bucket may hold on the fast path
 constexpr int LB3 = 10;           // bits of the in-LDS counting sort of B'
 constexpr int NB3 = 1 << LB3;
-constexpr int CB3 = 16;           // bits of the semi-join's cell bitmaps
+constexpr int CB3 = 15;           // bits of the semi-join's cell bitmaps
 constexpr int LCAP3 = 512;        // entries of each semi-join list
 constexpr int FB3 = 2048;         // B' keys staged per pass of the exact fallback
 constexpr int NTS = 256;          // threads of the small-search kernel

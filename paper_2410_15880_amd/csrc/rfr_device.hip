@@ -750,7 +750,7 @@ struct JoinLds {
     static constexpr uint32_t NWD = (1u << CB3) / 32;  // bitmap words
     union {
         struct {
-            uint32_t bm[NWD];
+            uint32_t bm[2 * NWD];  // cells of B', then cells LA's windows meet
             uint64_t la[LCAP3];
             uint64_t lb[LCAP3];
         } sj;
@@ -803,7 +803,8 @@ __device__ __forceinline__ void join_semi(const JobArgs &J, uint32_t s, int b, i
     const uint32_t NS = 1u << LB;
     const int shc = 64 - LB - CB3;
     const int tid = threadIdx.x;
-    uint32_t *bm = L.u.sj.bm;
+    uint32_t *bm = L.u.sj.bm;         // cells of B' keys
+    uint32_t *bmA = L.u.sj.bm + NWD;  // cells LA's windows meet
     uint64_t *LA = L.u.sj.la;
     uint64_t *LBl = L.u.sj.lb;
     if (na > CAP3 || nb > CAP3) {
@@ -828,7 +829,7 @@ __device__ __forceinline__ void join_semi(const JobArgs &J, uint32_t s, int b, i
         // is read first with no branch (the reads overlap; an unused slot reads
         // a stale but in-range cell), the bit tests follow; the rare keys within
         // a window of their cell's edge take a second pass for the neighbour.
-        uint32_t hits = 0, edge = 0;
+        uint32_t hits = 0, elo = 0, ehi = 0;
         {
             uint32_t cl[KP3], wd[KP3];
 #pragma unroll
@@ -841,43 +842,36 @@ __device__ __forceinline__ void join_semi(const JobArgs &J, uint32_t s, int b, i
                 const bool live = tid + k * NT3 < na;
                 const uint64_t off = kk[0][k] & om;
                 hits |= (uint32_t)(live && ((wd[k] >> (cl[k] & 31)) & 1u)) << k;
-                edge |= (uint32_t)(live && (off < t_hi || om - off < t_lo)) << k;
+                elo |= (uint32_t)(live && off < t_hi) << k;
+                ehi |= (uint32_t)(live && om - off < t_lo) << k;
             }
-            edge &= ~hits;
         }
-        if (edge) {
+        if ((elo | ehi) & ~hits) {
 #pragma unroll
             for (int k = 0; k < KP3; ++k) {  // static slot indices keep kk in registers
-                if (!((edge >> k) & 1u)) continue;
-                bool lo, hi;
-                cell_edges(kk[0][k], shc, t_lo, t_hi, lo, hi);
-                if (window_hits<NC>(bm, dig(kk[0][k], shc, NC - 1), lo, hi)) hits |= 1u << k;
+                if (!(((elo | ehi) & ~hits) >> k & 1u)) continue;
+                if (window_hits<NC>(bm, dig(kk[0][k], shc, NC - 1), (elo >> k) & 1u, (ehi >> k) & 1u))
+                    hits |= 1u << k;
             }
         }
+        // append the hits to LA and mark the cells their windows meet
         uint32_t o = wave_append(&L.nl[0], __popc(hits));
 #pragma unroll
         for (int k = 0; k < KP3; ++k)
             if ((hits >> k) & 1u) {
                 if (o < LCAP3) LA[o] = kk[0][k];
                 ++o;
+                mark_window<NC>(bmA, dig(kk[0][k], shc, NC - 1), (elo >> k) & 1u, (ehi >> k) & 1u);
             }
         __syncthreads();
         const uint32_t nla = L.nl[0];
         if (nla <= LCAP3) {
-            // the same bitmap, now of the cells LA's windows meet; B' keys in them
-            for (uint32_t i = tid; i < NWD; i += NT3) bm[i] = 0;
-            __syncthreads();
-            for (uint32_t i = tid; i < nla; i += NT3) {
-                bool lo, hi;
-                cell_edges(LA[i], shc, t_lo, t_hi, lo, hi);
-                mark_window<NC>(bm, dig(LA[i], shc, NC - 1), lo, hi);
-            }
-            __syncthreads();
+            // B' keys in those cells
             uint32_t bh = 0, cl[KP3], wd[KP3];
 #pragma unroll
             for (int k = 0; k < KP3; ++k) cl[k] = dig(kk[1][k], shc, NC - 1);
 #pragma unroll
-            for (int k = 0; k < KP3; ++k) wd[k] = bm[cl[k] >> 5];
+            for (int k = 0; k < KP3; ++k) wd[k] = bmA[cl[k] >> 5];
 #pragma unroll
             for (int k = 0; k < KP3; ++k)
                 bh |= (uint32_t)(tid + k * NT3 < nb && ((wd[k] >> (cl[k] & 31)) & 1u)) << k;
@@ -944,7 +938,7 @@ __device__ __forceinline__ void join_sub(const JobArgs &J, uint32_t s, int b, in
     if constexpr (SORT_OUT) {
         for (int i = tid; i < NB3; i += NT3) L.bin[i] = 0;
     } else {
-        for (uint32_t i = tid; i < JoinLds::NWD; i += NT3) L.u.sj.bm[i] = 0;
+        for (uint32_t i = tid; i < 2 * JoinLds::NWD; i += NT3) L.u.sj.bm[i] = 0;
         if (tid < 2) L.nl[tid] = 0;
     }
     uint32_t n[2];

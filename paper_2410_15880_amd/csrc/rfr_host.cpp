@@ -425,15 +425,12 @@ static uint64_t weight_of(dd v) {
     return hi_int + (uint64_t)(int64_t)fr;
 }
 
-rfr_status prepare_elements(Prepared &P, std::string &err) {
+// Roots of P.prim on the host: FP64 Aberth from Newton-polygon starting
+// points, complex double-double polish and inclusion radius of every root, and
+// for a disc meeting the real axis the real polish and its radius.  The same
+// records as the device root finder produces.
+static void host_roots(const Prepared &P, std::vector<RootOut> &ro) {
     const int d = (int)P.prim.size() - 1;
-    P.reals.clear();
-    P.pairs.clear();
-    P.w.clear();
-    if (d < 1) {
-        P.n = P.r = 0;
-        return RFR_OK;
-    }
     std::vector<double> ad(d + 1);
     std::vector<dd> add(d + 1);
     for (int i = 0; i <= d; ++i) {
@@ -447,14 +444,38 @@ rfr_status prepare_elements(Prepared &P, std::string &err) {
         z = initial_points(ad);
         aberth(ad, z, 400);
     }
-    // polish every root in complex double-double and take its inclusion disc
-    std::vector<cdd> zc(d);
-    std::vector<Disc> D(d);
+    ro.assign(d, RootOut());
     for (int i = 0; i < d; ++i) {
         cdd c{mkdd(z[i].real()), mkdd(z[i].imag())};
         c = polish_c(add, c, 6);
-        zc[i] = c;
-        D[i] = {cplx(to_d(c.re), to_d(c.im)), newton_c(add, c).radius};
+        const double r = newton_c(add, c).radius;
+        RootOut &o = ro[i];
+        o.re_hi = c.re.hi;
+        o.re_lo = c.re.lo;
+        o.im_hi = c.im.hi;
+        o.im_lo = c.im.lo;
+        o.r = r;
+        o.x_hi = o.x_lo = 0;
+        o.rx = INFINITY;
+        if (std::fabs(to_d(c.im)) <= r) {
+            const dd x = polish_r(add, c.re, 6);
+            o.x_hi = x.hi;
+            o.x_lo = x.lo;
+            o.rx = newton_r(add, x).radius;
+        }
+    }
+}
+
+rfr_status finish_elements(Prepared &P, const RootOut *ro, std::string &err) {
+    const int d = (int)P.prim.size() - 1;
+    P.reals.clear();
+    P.pairs.clear();
+    P.w.clear();
+    std::vector<cdd> zc(d);
+    std::vector<Disc> D(d);
+    for (int i = 0; i < d; ++i) {
+        zc[i] = cdd{dd{ro[i].re_hi, ro[i].re_lo}, dd{ro[i].im_hi, ro[i].im_lo}};
+        D[i] = {cplx(to_d(zc[i].re), to_d(zc[i].im)), ro[i].r};
     }
     rfr_status st = RFR_OK;
     if (!discs_disjoint(D)) {
@@ -469,8 +490,8 @@ rfr_status prepare_elements(Prepared &P, std::string &err) {
     std::vector<Disc> F;
     for (int i = 0; i < d; ++i) {
         if (std::fabs(D[i].c.imag()) <= D[i].r) {
-            dd x = polish_r(add, zc[i].re, 6);
-            double rx = newton_r(add, x).radius;
+            const dd x{ro[i].x_hi, ro[i].x_lo};
+            const double rx = ro[i].rx;
             reals.push_back(x);
             rr.push_back(rx);
             F.push_back({cplx(to_d(x), 0), rx});
@@ -561,6 +582,20 @@ rfr_status prepare_elements(Prepared &P, std::string &err) {
     P.t_lo = (uint64_t)P.n + E;
     P.t_hi = E;
     return RFR_OK;
+}
+
+rfr_status prepare_elements(Prepared &P, std::string &err) {
+    const int d = (int)P.prim.size() - 1;
+    P.reals.clear();
+    P.pairs.clear();
+    P.w.clear();
+    if (d < 1) {
+        P.n = P.r = 0;
+        return RFR_OK;
+    }
+    std::vector<RootOut> ro;
+    host_roots(P, ro);
+    return finish_elements(P, ro.data(), err);
 }
 
 rfr_status prepare(const int64_t *coeffs, int degree, Prepared &P, std::string &err) {

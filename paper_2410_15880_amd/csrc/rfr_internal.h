@@ -59,9 +59,21 @@ struct Factored {
 // Split content, sign and x-power; validate.  Section 2 preconditions.
 rfr_status normalise(const int64_t *coeffs, int degree, Prepared &P, std::string &err);
 
+// One root of P.prim: complex double-double value and inclusion radius; for a
+// disc meeting the real axis also the real polished value and its radius
+// (rx = +inf otherwise).
+struct RootOut {
+    double re_hi, re_lo, im_hi, im_lo, r, x_hi, x_lo, rx;
+};
+
 // Roots (FP64 Aberth + double-double Newton polish, certified by disjoint
 // inclusion discs), elements, weights and window (Sections 2 and 3.3).
 rfr_status prepare_elements(Prepared &P, std::string &err);
+
+// The part of prepare_elements after the roots: check the discs, classify,
+// pair, order the elements, weights and window, from the d root records ro
+// (found on the host or on the device).  P.prim must have degree >= 1.
+rfr_status finish_elements(Prepared &P, const RootOut *ro, std::string &err);
 
 // normalise + prepare_elements.
 rfr_status prepare(const int64_t *coeffs, int degree, Prepared &P, std::string &err);

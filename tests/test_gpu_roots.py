@@ -1,0 +1,119 @@
+"""GPU parity of the device root finder (batched path, roots -> elements).
+
+The device finds every root of each polynomial (FP64 Aberth, double-double
+Newton polish, inclusion radii); the host checks the discs and forms the
+elements, weights and window.  Compared with the oracle's 400-bit roots:
+same element count and real count, every weight within the window's own
+bound of the exact one, and the window conservative for the quantisation.
+"""
+import random
+
+import pytest
+
+from oracle import rfr_ref as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+MOD = 1 << 64
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2410_15880_amd as R
+    R.lib()
+    return R
+
+
+@pytest.fixture(scope="module")
+def ctx(R):
+    c = R.Context(0)
+    yield c
+    c.close()
+
+
+def _signed(x):
+    return ((x + (1 << 63)) % MOD) - (1 << 63)
+
+
+def _check_against_oracle(got, coeffs):
+    cont, k, prim = O.normalise(coeffs)
+    ts, groups, deltas = O.elements(prim)
+    ow = O.weights(prim, ts)
+    assert got["n"] == len(ts)
+    for a, b in zip(got["w"], ow):
+        assert abs(_signed(a - b)) <= got["t_hi"]
+    assert got["t_lo"] >= got["n"] + got["t_hi"]
+
+
+def test_device_weights_match_oracle_batch_mix(R, ctx):
+    rng = random.Random(11)
+    polys = [w.coeffs for w in rng.sample(W.config_batch(), 64)]
+    polys += [r.work.coeffs for r in W.config_stream(120, rate_per_s=1.0)[::6]]
+    say("prepare_batch of %d" % len(polys))
+    got = ctx.prepare_batch(polys)
+    used = 0
+    for c, g in zip(polys, got):
+        assert not isinstance(g, Exception), g
+        _check_against_oracle(g, c)
+        used += g["device_roots"]
+    # the host fallback is for the rare polynomial the device roots do not certify
+    assert used >= 0.95 * len(polys), (used, len(polys))
+
+
+def test_device_weights_match_host_stage(R, ctx):
+    # device roots and host roots give the same elements; weights agree within
+    # the window
+    polys = [w.coeffs for w in W.config_large()] + [w.coeffs for w in W.config_mid()]
+    say("device vs host, %d polys" % len(polys))
+    got = ctx.prepare_batch(polys)
+    for c, g in zip(polys, got):
+        h = R.weights(c)
+        assert g["n"] == h["n"]
+        bound = max(g["t_hi"], h["t_hi"])
+        for a, b in zip(g["w"], h["w"]):
+            assert abs(_signed(a - b)) <= bound
+
+
+def test_device_roots_edge_cases(R, ctx):
+    polys = [
+        [6, -5, 1],                  # x^2 - 5x + 6 (two real roots)
+        [1, 0, 1],                   # x^2 + 1 (one pair)
+        [-2, 0, 1],                  # irrational pair of reals
+        [3, 7],                      # linear: host only
+        [0, 6, 6, -36],              # x-power split off, then degree 2
+        [1, -2, 1],                  # not square-free
+        [1, 0, -10, 0, 1],           # x^4 - 10x^2 + 1
+        [-1, 0, 0, 0, 0, 0, 1],      # x^6 - 1
+    ]
+    say("edge cases")
+    got = ctx.prepare_batch(polys)
+    for c, g in zip(polys, got):
+        if c == [1, -2, 1]:
+            assert isinstance(g, R.RFRError) and g.name == "RFR_ENOTSQFREE"
+            continue
+        assert not isinstance(g, Exception), (c, g)
+        _check_against_oracle(g, c)
+    assert got[3]["device_roots"] is False  # linear
+    assert got[0]["device_roots"] and got[1]["device_roots"]
+
+
+def test_device_roots_high_degree(R, ctx):
+    # degree 200 with small coefficients: 200 device threads, one per root
+    rng = random.Random(21)
+    c = [rng.randint(-9, 9) for _ in range(201)]
+    c[0] = c[0] or 1
+    c[-1] = c[-1] or 1
+    say("degree 200")
+    g = ctx.prepare_batch([c])[0]
+    if isinstance(g, R.RFRError):
+        # only a genuine limit may stop it (more than 128 elements)
+        assert g.name == "RFR_EOVERFLOW"
+        return
+    assert g["device_roots"]
+    _check_against_oracle(g, c)
