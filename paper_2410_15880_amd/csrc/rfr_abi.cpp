@@ -9,6 +9,7 @@
 #include <new>
 
 #include "rfr_ctx.h"
+#include "rfr_roots.h"
 
 namespace rfr {
 
@@ -70,9 +71,59 @@ rfr_status ensure_workspace(rfr_ctx *ctx, Slot &s, size_t need) {
     return RFR_OK;
 }
 
+// RootBuf layout: coefficients [0, O_JOB) | job [O_JOB, O_OUT) | records.
+constexpr size_t ROOT_O_JOB = ((RFR_MAX_DEGREE + 1) * 8 + 255) & ~(size_t)255;
+constexpr size_t ROOT_O_OUT = ROOT_O_JOB + 256;
+constexpr size_t ROOT_BYTES = ROOT_O_OUT + RFR_MAX_DEGREE * sizeof(RootOut);
+static_assert(sizeof(RootJob) <= 256, "job descriptor fits its slot");
+
+rfr_status rootbuf_init(RootBuf &b, hipStream_t stream) {
+    b.own_stream = stream == nullptr;
+    if (b.own_stream) {
+        if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess)
+            return fail(RFR_EDEVICE, "hipStreamCreate failed");
+    }
+    b.stream = stream;
+    if (hipMalloc((void **)&b.dev, ROOT_BYTES) != hipSuccess) {
+        b.dev = nullptr;
+        return fail(RFR_ENOMEM, "hipMalloc of the root buffer failed");
+    }
+    if (hipHostMalloc((void **)&b.host, ROOT_BYTES, hipHostMallocDefault) != hipSuccess) {
+        b.host = nullptr;
+        return fail(RFR_ENOMEM, "hipHostMalloc of the root buffer failed");
+    }
+    return RFR_OK;
+}
+
+void rootbuf_free(RootBuf &b) {
+    if (b.dev) (void)hipFree(b.dev);
+    if (b.host) (void)hipHostFree(b.host);
+    if (b.own_stream && b.stream) (void)hipStreamDestroy(b.stream);
+    b = RootBuf();
+}
+
+rfr_status prepare_dev(RootBuf &b, const int64_t *coeffs, int degree, Prepared &P, std::string &err) {
+    rfr_status st = normalise(coeffs, degree, P, err);
+    if (st != RFR_OK) return st;
+    const int d = (int)P.prim.size() - 1;
+    if (d >= 2 && b.dev && b.host) {
+        std::memcpy(b.host, P.prim.data(), (size_t)(d + 1) * 8);
+        *(RootJob *)(b.host + ROOT_O_JOB) = RootJob{(const int64_t *)b.dev, d, (RootOut *)(b.dev + ROOT_O_OUT)};
+        bool ok = hipMemcpyAsync(b.dev, b.host, ROOT_O_OUT, hipMemcpyHostToDevice, b.stream) == hipSuccess;
+        ok = ok && launch_roots((const RootJob *)(b.dev + ROOT_O_JOB), 1, b.stream) == hipSuccess;
+        ok = ok && hipMemcpyAsync(b.host + ROOT_O_OUT, b.dev + ROOT_O_OUT, (size_t)d * sizeof(RootOut),
+                                  hipMemcpyDeviceToHost, b.stream) == hipSuccess;
+        ok = ok && hipStreamSynchronize(b.stream) == hipSuccess;
+        if (ok && finish_elements(P, (const RootOut *)(b.host + ROOT_O_OUT), err) == RFR_OK) return RFR_OK;
+        err.clear();
+    }
+    return prepare_elements(P, err);
+}
+
 rfr_status slot_init(rfr_ctx *ctx, Slot &s) {
     if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess)
         return fail(RFR_EDEVICE, "hipStreamCreate failed");
+    if (rootbuf_init(s.roots, s.stream) != RFR_OK) return RFR_ENOMEM;
     if (hipMalloc(&s.cand_dev, 2 * ctx->cap * sizeof(uint64_t) + 256) != hipSuccess)
         return fail(RFR_ENOMEM, "hipMalloc of the candidate buffer failed");
     s.count_dev = (uint64_t *)((char *)s.cand_dev + 2 * ctx->cap * sizeof(uint64_t));
@@ -89,6 +140,7 @@ void slot_free(rfr_ctx *ctx, Slot &s) {
     }
     if (s.cand_dev) (void)hipFree(s.cand_dev);
     if (s.host) (void)hipHostFree(s.host);
+    rootbuf_free(s.roots);
     if (s.stream) (void)hipStreamDestroy(s.stream);
     s = Slot();
 }
@@ -160,7 +212,7 @@ rfr_status factor_on_slot(rfr_ctx *ctx, Slot &s, const int64_t *coeffs, int degr
     double t0 = now_ms();
     Prepared P;
     std::string err;
-    rfr_status st = prepare(coeffs, degree, P, err);
+    rfr_status st = prepare_dev(s.roots, coeffs, degree, P, err);
     if (st != RFR_OK) return fail(st, err);
     double t1 = now_ms();
     Factored F;

@@ -20,8 +20,18 @@ namespace rfr {
 
 // One device lane of work: a stream, a search workspace (grown on demand) and
 // candidate buffers (device + pinned host).
+// Buffers for finding one polynomial's roots on the device: coefficients,
+// job descriptor and root records, pinned staging of the same layout.
+struct RootBuf {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    char *dev = nullptr;
+    char *host = nullptr;
+};
+
 struct Slot {
     hipStream_t stream = nullptr;
+    RootBuf roots;
     void *ws = nullptr;
     size_t ws_bytes = 0;
     uint64_t *cand_dev = nullptr;
@@ -80,6 +90,14 @@ void slot_free(rfr_ctx *ctx, Slot &s);
 rfr_status search_on_slot(rfr_ctx *ctx, Slot &s, const Prepared &P, std::vector<Pat> &cands);
 size_t choose_workspace(int n, size_t avail);
 void tuning_autoload();
+
+// Root buffers on a given stream (nullptr: the buffers get a stream of their own).
+rfr_status rootbuf_init(RootBuf &b, hipStream_t stream);
+void rootbuf_free(RootBuf &b);
+// normalise + elements, weights and window with the roots found on the device
+// (one workgroup on b.stream); the host finds them itself for degree < 2 or
+// when the device roots fail the disc checks.
+rfr_status prepare_dev(RootBuf &b, const int64_t *coeffs, int degree, Prepared &P, std::string &err);
 rfr_status factor_on_slot(rfr_ctx *ctx, Slot &s, const int64_t *coeffs, int degree, rfr_result **out);
 void batch_release(rfr_ctx *ctx);
 StageEvents *profile_events(rfr_ctx *ctx, int k);

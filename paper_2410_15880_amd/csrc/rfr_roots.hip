@@ -213,9 +213,9 @@ __global__ __launch_bounds__(ROOT_THREADS) void k_roots(const RootJob *jobs, int
     __shared__ double s_aa[RFR_MAX_DEGREE + 1];  // |coefficients| (FP64)
     __shared__ D2 s_add[RFR_MAX_DEGREE + 1];     // coefficients (double-double, exact)
     __shared__ Z s_z[RFR_MAX_DEGREE];            // current iterate
-    __shared__ double s_lg[RFR_MAX_DEGREE + 1];
-    __shared__ int s_idx[RFR_MAX_DEGREE + 1];
-    __shared__ int s_hull[RFR_MAX_DEGREE + 1];
+    __shared__ double s_lg[RFR_MAX_DEGREE + 1];   // log|a_i| (a_i != 0)
+    __shared__ int s_hull[RFR_MAX_DEGREE + 1];    // hull vertices (coefficient indices)
+    __shared__ int s_nh;
     if (d < 2 || d > RFR_MAX_DEGREE) return;  // the host handles linear inputs
 
     for (int i = tid; i <= d; i += ROOT_THREADS) {
@@ -223,54 +223,75 @@ __global__ __launch_bounds__(ROOT_THREADS) void k_roots(const RootJob *jobs, int
         s_a[i] = (double)c;
         s_add[i] = from_i64(c);
         s_aa[i] = fabs(to_d(s_add[i]));
+        s_lg[i] = c != 0 ? log(fabs((double)c)) : 0.0;
     }
     __syncthreads();
     // 1. starting points: one circle per edge of the upper convex hull of
-    //    (i, log|a_i|), radius from the edge's slope
+    //    (i, log|a_i|) over the nonzero coefficients, radius from the edge's
+    //    slope; the hull walk is serial, the points are set in parallel
     if (tid == 0) {
-        int m = 0;
-        for (int i = 0; i <= d; ++i)
-            if (s_a[i] != 0) {
-                s_idx[m] = i;
-                s_lg[m] = log(fabs(s_a[i]));
-                ++m;
-            }
         int h = 0;
-        for (int k = 0; k < m; ++k) {
+        for (int k = 0; k <= d; ++k) {
+            if (s_a[k] == 0) continue;
             while (h >= 2) {
                 const int i1 = s_hull[h - 2], i2 = s_hull[h - 1];
-                const double x1 = s_idx[i1], y1 = s_lg[i1], x2 = s_idx[i2], y2 = s_lg[i2], x3 = s_idx[k],
-                             y3 = s_lg[k];
-                if ((x2 - x1) * (y3 - y1) - (y2 - y1) * (x3 - x1) >= 0) --h;
+                if ((double)(i2 - i1) * (s_lg[k] - s_lg[i1]) - (s_lg[i2] - s_lg[i1]) * (double)(k - i1) >= 0) --h;
                 else break;
             }
             s_hull[h++] = k;
         }
-        const double two_pi = 6.283185307179586;
-        int o = 0;
-        for (int e = 0; e + 1 < h; ++e) {
-            const int k = s_idx[s_hull[e]], l = s_idx[s_hull[e + 1]];
-            const double u = exp((s_lg[s_hull[e]] - s_lg[s_hull[e + 1]]) / (l - k));
-            for (int q = 0; q < l - k; ++q) {
-                const double ang = two_pi * q / (l - k) + two_pi * k / d + 0.4;
-                double sn, cs;
-                sincos(ang, &sn, &cs);
-                s_z[o++] = Z{u * cs, u * sn};
-            }
-        }
+        s_nh = h;
     }
     __syncthreads();
-    // 2. simultaneous Aberth-Ehrlich iteration
+    if (tid < d) {
+        // root slot tid lies on the edge [k, l) with k <= tid < l (a_0, a_d != 0,
+        // so the hull spans 0..d and its edges cover every slot once)
+        int e = 0;
+        while (e + 2 < s_nh && s_hull[e + 1] <= tid) ++e;
+        const int k = s_hull[e], l = s_hull[e + 1], q = tid - k;
+        const double two_pi = 6.283185307179586;
+        const double u = exp((s_lg[k] - s_lg[l]) / (l - k));
+        const double ang = two_pi * q / (l - k) + two_pi * k / d + 0.4;
+        double sn, cs;
+        sincos(ang, &sn, &cs);
+        s_z[tid] = Z{u * cs, u * sn};
+    }
+    __syncthreads();
+    // 2. simultaneous Aberth-Ehrlich iteration.  A root stops when its step is
+    //    below 1e-13 of its modulus, or small and no longer shrinking (the
+    //    FP64 evaluation noise floor); the double-double polish takes it from
+    //    there.  The workgroup iterates until every root has stopped.
     Z z = tid < d ? s_z[tid] : Z{0, 0};
     bool done = tid >= d;
+    double prev = INFINITY;
     for (int it = 0; it < ROOT_MAXIT; ++it) {
         Z wc{0, 0};
         bool upd = false;
         if (!done) {
             const Z N = newton_ratio(s_a, d, z);
-            Z S{0, 0};
-            for (int q = 0; q < d; ++q)
-                if (q != tid) S = zadd(S, zdiv(Z{1, 0}, zsub(z, s_z[q])));
+            // S = sum over the other roots of 1 / (z - z_q) = conj(w) / |w|^2,
+            // four independent partial sums so the divisions overlap; the own
+            // term is replaced by w = 1 and taken out at the end
+            double sr[4] = {0, 0, 0, 0}, si[4] = {0, 0, 0, 0};
+            int q = 0;
+            for (; q + 4 <= d; q += 4) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    Z w = zsub(z, s_z[q + u]);
+                    if (q + u == tid) w = Z{1, 0};
+                    const double inv = 1.0 / (w.re * w.re + w.im * w.im);
+                    sr[u] += w.re * inv;
+                    si[u] -= w.im * inv;
+                }
+            }
+            for (; q < d; ++q) {
+                Z w = zsub(z, s_z[q]);
+                if (q == tid) w = Z{1, 0};
+                const double inv = 1.0 / (w.re * w.re + w.im * w.im);
+                sr[0] += w.re * inv;
+                si[0] -= w.im * inv;
+            }
+            const Z S{(sr[0] + sr[1]) + (sr[2] + sr[3]) - 1.0, (si[0] + si[1]) + (si[2] + si[3])};
             wc = zdiv(N, zsub(Z{1, 0}, zmul(N, S)));
             if (!finite(wc)) done = true;
             else upd = true;
@@ -279,7 +300,9 @@ __global__ __launch_bounds__(ROOT_THREADS) void k_roots(const RootJob *jobs, int
         if (upd) {
             z = zsub(z, wc);
             s_z[tid] = z;
-            if (zabs(wc) <= 1e-15 * fmax(zabs(z), 1e-300)) done = true;
+            const double step = zabs(wc), scale = fmax(zabs(z), 1e-300);
+            if (step <= 1e-13 * scale || (step <= 1e-9 * scale && step >= 0.5 * prev)) done = true;
+            prev = step;
         }
         if (!__syncthreads_or(!done)) break;
     }
@@ -288,10 +311,12 @@ __global__ __launch_bounds__(ROOT_THREADS) void k_roots(const RootJob *jobs, int
     C2 c{mk(z.re), mk(z.im)};
     C2 step;
     double radius;
+    // Newton converges quadratically from the FP64 root: once a step is below
+    // 1e-20 of the root the next would be below double-double resolution
     for (int k = 0; k < ROOT_POLISH; ++k) {
         newton_c(s_add, s_aa, d, c, step, radius);
         c = csub(c, step);
-        if (cabs_d(step) <= 1e-31 * fmax(cabs_d(c), 1e-300)) break;
+        if (cabs_d(step) <= 1e-20 * fmax(cabs_d(c), 1e-300)) break;
     }
     newton_c(s_add, s_aa, d, c, step, radius);
     RootOut out;
@@ -309,7 +334,7 @@ __global__ __launch_bounds__(ROOT_THREADS) void k_roots(const RootJob *jobs, int
         for (int k = 0; k < ROOT_POLISH; ++k) {
             newton_r(s_add, s_aa, d, x, sx, rx);
             x = sub(x, sx);
-            if (fabs(to_d(sx)) <= 1e-31 * fmax(fabs(to_d(x)), 1e-300)) break;
+            if (fabs(to_d(sx)) <= 1e-20 * fmax(fabs(to_d(x)), 1e-300)) break;
         }
         newton_r(s_add, s_aa, d, x, sx, rx);
         out.x_hi = x.hi;

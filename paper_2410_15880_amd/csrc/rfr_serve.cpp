@@ -89,14 +89,14 @@ static void release_slot(rfr_ctx *ctx, Slot *s) {
     ctx->cv_slot.notify_all();
 }
 
-static void serve_one(rfr_ctx *ctx, Request *r) {
+static void serve_one(rfr_ctx *ctx, RootBuf &rb, Request *r) {
     double t0 = now_ms();
     Prepared P;
     std::string err;
     Factored F;
     std::vector<Pat> cands;
     rfr_result *res = nullptr;
-    rfr_status st = prepare(r->coeffs.data(), (int)r->coeffs.size() - 1, P, err);
+    rfr_status st = prepare_dev(rb, r->coeffs.data(), (int)r->coeffs.size() - 1, P, err);
     if (st != RFR_OK) st = fail(st, err);
     double t1 = now_ms(), t2 = t1;
     if (st == RFR_OK && P.n <= 1) {
@@ -140,17 +140,22 @@ static void serve_one(rfr_ctx *ctx, Request *r) {
 
 static void worker_loop(rfr_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
+    // roots of this worker's requests are found on the device on a stream of
+    // its own (the host finds them if these buffers cannot be had)
+    RootBuf rb;
+    if (rootbuf_init(rb, nullptr) != RFR_OK) rootbuf_free(rb);
     for (;;) {
         Request *r = nullptr;
         {
             std::unique_lock<std::mutex> lk(ctx->mu);
             ctx->cv_work.wait(lk, [&] { return ctx->stopping || !ctx->queue.empty(); });
-            if (ctx->queue.empty()) return;  // stopping and drained
+            if (ctx->queue.empty()) break;  // stopping and drained
             r = ctx->queue.front();
             ctx->queue.pop_front();
         }
-        serve_one(ctx, r);
+        serve_one(ctx, rb, r);
     }
+    rootbuf_free(rb);
 }
 
 }  // namespace rfr
