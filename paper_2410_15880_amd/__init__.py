@@ -12,6 +12,8 @@ import ctypes as C
 import os
 from typing import List, Optional, Sequence, Tuple
 
+import numpy as np
+
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "_lib", "librfr.so")
 
@@ -114,16 +116,22 @@ def _check(st: int):
 
 
 def _i64(coeffs: Sequence[int]):
-    vals = [int(c) for c in coeffs]
-    return (C.c_int64 * len(vals))(*vals)
+    """int64 array for the C ABI (raises OverflowError for values outside int64)."""
+    arr = np.fromiter((int(c) for c in coeffs), dtype=np.int64)
+    if arr.size == 0:
+        arr = np.zeros(1, dtype=np.int64)
+    return np.ctypeslib.as_ctypes(arr)
 
 
 def _unpack(rp) -> dict:
     r = rp.contents
+    nf = int(r.nfactors)
+    degs = np.ctypeslib.as_array(r.degrees, shape=(nf,)).tolist() if nf else []
+    total = sum(d + 1 for d in degs)
+    co = np.ctypeslib.as_array(r.coeffs, shape=(total,)).tolist() if total else []
     facs, k = [], 0
-    for i in range(r.nfactors):
-        d = r.degrees[i]
-        facs.append(tuple(int(r.coeffs[k + j]) for j in range(d + 1)))
+    for d in degs:
+        facs.append(tuple(co[k:k + d + 1]))
         k += d + 1
     out = {"content": int(r.content), "factors": facs, "n": int(r.n_elements), "r": int(r.n_real),
            "n_candidates": int(r.n_candidates), "n_confirmed": int(r.n_confirmed),
