@@ -176,6 +176,20 @@ rfr_status rfr_load_tuning(const char *path);
 /* ------------------------------------------------------------------ results */
 
 void rfr_result_free(rfr_result *res);
+
+/* Flatten `count` results for callers that convert many at once (a batch):
+ * content[i] and nfactors[i] per result, the degrees of all factors result
+ * after result into degrees[0..), their coefficients (ascending, factor after
+ * factor) into coeffs[0..).  A null res[i] counts as content 0 with no factors.
+ * The totals are returned in *ndeg and *ncoef; with degrees or coeffs NULL
+ * nothing else is written (a size query).  RFR_EINVAL if deg_cap or coef_cap
+ * is below the totals (nothing written then).  The results stay owned by the
+ * caller. */
+rfr_status rfr_results_pack(rfr_result *const *res, int count, int64_t *content, int32_t *nfactors,
+                            int32_t *degrees, size_t deg_cap, int64_t *coeffs, size_t coef_cap, size_t *ndeg,
+                            size_t *ncoef);
+/* rfr_result_free on res[0..count) (null entries are skipped). */
+void rfr_results_free(rfr_result *const *res, int count);
 const char *rfr_strerror(rfr_status st);
 const char *rfr_last_error(void);
 

@@ -9,6 +9,7 @@ library raises.
 from __future__ import annotations
 
 import ctypes as C
+import itertools
 import os
 from typing import List, Optional, Sequence, Tuple
 
@@ -30,7 +31,7 @@ EXPORTS = [
     "rfr_strerror", "rfr_last_error", "rfr_weights", "rfr_recombine_workspace_bytes",
     "rfr_recombine_dev", "rfr_expand_workspace_bytes", "rfr_expand_dev",
     "rfr_profile", "rfr_profile_read", "rfr_recombine_min_workspace_bytes",
-    "rfr_autotune", "rfr_load_tuning", "rfr_prepare_batch",
+    "rfr_autotune", "rfr_load_tuning", "rfr_prepare_batch", "rfr_results_pack", "rfr_results_free",
 ]
 
 
@@ -85,6 +86,8 @@ def lib():
         "rfr_poll": ([P, u64, C.POINTER(RP), C.POINTER(C.c_double)], C.c_int),
         "rfr_serve_stop": ([P], C.c_int),
         "rfr_result_free": ([RP], None),
+        "rfr_results_pack": ([C.POINTER(RP), C.c_int, P, P, P, sz, P, sz, C.POINTER(sz), C.POINTER(sz)], C.c_int),
+        "rfr_results_free": ([C.POINTER(RP), C.c_int], None),
         "rfr_strerror": ([C.c_int], C.c_char_p),
         "rfr_last_error": ([], C.c_char_p),
         "rfr_weights": ([C.POINTER(i64), C.c_int, C.POINTER(u64), C.POINTER(i32), C.POINTER(i32),
@@ -139,6 +142,46 @@ def _unpack(rp) -> dict:
            "ms_search": r.ms_search, "ms_confirm": r.ms_confirm}
     lib().rfr_result_free(rp)
     return out
+
+
+def _flatten(polys: Sequence[Sequence[int]]):
+    """Degrees (int32) and all coefficients back to back (int64) of a batch
+    (raises OverflowError for values outside int64)."""
+    n = len(polys)
+    degs = np.fromiter((len(p) - 1 for p in polys), dtype=np.int32, count=n)
+    total = int(degs.sum(dtype=np.int64)) + n
+    flat = np.fromiter(itertools.chain.from_iterable(polys), dtype=np.int64, count=total)
+    if flat.size == 0:
+        flat = np.zeros(1, dtype=np.int64)
+    return degs, flat
+
+
+def _unpack_many(outs, sts, n: int) -> List:
+    """(content, factors) or RFRError per entry of a batch's results (one
+    flattening call instead of one conversion per result)."""
+    L = lib()
+    nd, nc = C.c_size_t(), C.c_size_t()
+    _check(L.rfr_results_pack(outs, n, None, None, None, 0, None, 0, C.byref(nd), C.byref(nc)))
+    content = np.zeros(max(n, 1), dtype=np.int64)
+    nfac = np.zeros(max(n, 1), dtype=np.int32)
+    dg = np.zeros(max(nd.value, 1), dtype=np.int32)
+    co = np.zeros(max(nc.value, 1), dtype=np.int64)
+    _check(L.rfr_results_pack(outs, n, content.ctypes.data, nfac.ctypes.data, dg.ctypes.data, dg.size,
+                              co.ctypes.data, co.size, C.byref(nd), C.byref(nc)))
+    st = np.ctypeslib.as_array(sts, shape=(max(n, 1),))[:n].tolist()
+    content, nfac, dg, co = content.tolist(), nfac.tolist(), dg.tolist(), co.tolist()
+    res, kd, kc = [], 0, 0
+    for i in range(n):
+        if st[i] != RFR_OK:
+            res.append(RFRError(st[i], "batch entry %d" % i))
+            continue
+        facs = []
+        for d in dg[kd:kd + nfac[i]]:
+            facs.append(tuple(co[kc:kc + d + 1]))
+            kc += d + 1
+        kd += nfac[i]
+        res.append((content[i], facs))
+    return res
 
 
 TUNING_PATH = os.path.join(_PKG, "tuning", "mi355x.txt")
@@ -197,19 +240,15 @@ class Context:
     def factor_batch(self, polys: Sequence[Sequence[int]]) -> List:
         """List of (content, factors) or RFRError per polynomial."""
         n = len(polys)
-        flat = [int(c) for p in polys for c in p]
-        degs = (C.c_int32 * n)(*[len(p) - 1 for p in polys])
-        outs = (C.POINTER(Result) * n)()
-        sts = (C.c_int * n)()
-        _check(lib().rfr_factor_batch(self._h, n, _i64(flat), degs, outs, sts))
-        res = []
-        for i in range(n):
-            if sts[i] == RFR_OK:
-                u = _unpack(outs[i])
-                res.append((u["content"], u["factors"]))
-            else:
-                res.append(RFRError(sts[i], "batch entry %d" % i))
-        return res
+        degs, flat = _flatten(polys)
+        outs = (C.POINTER(Result) * max(n, 1))()
+        sts = (C.c_int * max(n, 1))()
+        _check(lib().rfr_factor_batch(self._h, n, flat.ctypes.data_as(C.POINTER(C.c_int64)),
+                                      degs.ctypes.data_as(C.POINTER(C.c_int32)), outs, sts))
+        try:
+            return _unpack_many(outs, sts, n)
+        finally:
+            lib().rfr_results_free(outs, n)
 
     def prepare_batch(self, polys: Sequence[Sequence[int]]) -> List:
         """Host stages of the batched path with device roots: per polynomial a

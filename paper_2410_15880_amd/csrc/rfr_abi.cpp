@@ -303,6 +303,42 @@ rfr_status rfr_factor(rfr_ctx *ctx, const int64_t *coeffs, int degree, rfr_resul
 
 void rfr_result_free(rfr_result *res) { std::free(res); }
 
+rfr_status rfr_results_pack(rfr_result *const *res, int count, int64_t *content, int32_t *nfactors,
+                            int32_t *degrees, size_t deg_cap, int64_t *coeffs, size_t coef_cap, size_t *ndeg,
+                            size_t *ncoef) {
+    if (count < 0 || (count > 0 && !res) || !ndeg || !ncoef) return fail(RFR_EINVAL, "bad arguments");
+    size_t nd = 0, nc = 0;
+    for (int i = 0; i < count; ++i) {
+        const rfr_result *r = res[i];
+        if (!r) continue;
+        nd += (size_t)r->nfactors;
+        for (int k = 0; k < r->nfactors; ++k) nc += (size_t)r->degrees[k] + 1;
+    }
+    *ndeg = nd;
+    *ncoef = nc;
+    if (!degrees || !coeffs) return RFR_OK;
+    if (!content || !nfactors || deg_cap < nd || coef_cap < nc) return fail(RFR_EINVAL, "buffers too small");
+    size_t od = 0, oc = 0;
+    for (int i = 0; i < count; ++i) {
+        const rfr_result *r = res[i];
+        content[i] = r ? r->content : 0;
+        nfactors[i] = r ? r->nfactors : 0;
+        if (!r) continue;
+        size_t m = 0;
+        for (int k = 0; k < r->nfactors; ++k) {
+            degrees[od++] = r->degrees[k];
+            m += (size_t)r->degrees[k] + 1;
+        }
+        std::memcpy(coeffs + oc, r->coeffs, m * sizeof(int64_t));
+        oc += m;
+    }
+    return RFR_OK;
+}
+
+void rfr_results_free(rfr_result *const *res, int count) {
+    for (int i = 0; res && i < count; ++i) std::free(res[i]);
+}
+
 const char *rfr_strerror(rfr_status st) {
     switch (st) {
         case RFR_OK: return "ok";

@@ -369,13 +369,18 @@ extern "C" rfr_status rfr_factor_batch(rfr_ctx *ctx, int count, const int64_t *c
     for (int k = 0; k < nL; ++k) {
         int na, nb;
         split_halves(P[large[k]].n, na, nb);
-        size_t bts = plan_job(na, nb, plans[k], BCAP + 1);
+        size_t bts = plan_job(na, nb, plans[k], BCAP + 1, true);
         wsoff[k + 1] = wsoff[k] + ((bts + 255) & ~(size_t)255);
     }
-    // descriptor block: JobArgs[nL] | bases | SmallJob[nS] | queue counter
+    // descriptor block: JobArgs[nL] | bases and tables | SmallJob[nS] | queue counter
     const size_t o_jobs = 0;
     const size_t o_bases = (o_jobs + sizeof(dev::JobArgs) * nL + 255) & ~(size_t)255;
-    const size_t bases_bytes = (size_t)dev::NSTAGES * (nL + 1) * 4;
+    size_t bases_bytes = 0;  // block offsets and block -> job tables of every stage
+    {
+        MultiLaunch T;
+        for (int k = 0; k < nL; ++k) T.add(plans[k], dev::JobArgs{});
+        bases_bytes = T.bases_bytes();
+    }
     const size_t o_small = (o_bases + bases_bytes + 255) & ~(size_t)255;
     const size_t o_queue = (o_small + sizeof(SmallJob) * nS + 255) & ~(size_t)255;
     const size_t desc_bytes = o_queue + 256;

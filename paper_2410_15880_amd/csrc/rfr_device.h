@@ -86,11 +86,16 @@ struct JobArgs {
 // Stages of the pipeline (kernel launches), in launch order.
 enum Stage { ST_INIT, ST_COUNT, ST_COLS, ST_BUCKETS, ST_ENUM, ST_TILE2, ST_JOIN, ST_RFEW, ST_RMANY, ST_PAIRS, NSTAGES };
 
+// Blocks per entry of a stage's block -> job table (see pick()).
+constexpr uint32_t PICK_GRP = 64;
+
 // Batch of jobs in device memory (see pick() in rfr_device.hip).
 struct Multi {
     const JobArgs *jobs;
-    const uint32_t *bases;  // [NSTAGES][njobs + 1]
+    const uint32_t *bases;      // [NSTAGES][njobs + 1]
     int njobs;
+    const uint32_t *groups;     // per stage: job of block g * PICK_GRP, g = 0..ceil(grid / PICK_GRP), then njobs - 1
+    uint32_t gofs[NSTAGES];     // start of each stage's table in groups
 };
 }  // namespace dev
 
@@ -121,6 +126,7 @@ struct MultiLaunch {
     std::vector<std::vector<uint32_t>> bases;  // [stage][job + 1]
     int maxB1 = 0, maxB2 = 0;
     void add(const JobPlan &P, const dev::JobArgs &J);
+    // bases, then the per-stage block -> job tables (bytes; see Multi)
     size_t bases_bytes() const;
     void pack_bases(uint32_t *dst) const;
     hipError_t launch(const dev::JobArgs *jobs_dev, const uint32_t *bases_dev, hipStream_t st,
@@ -149,7 +155,8 @@ void set_tune(int lg, Tune t);
 Tune get_tune(int lg);
 
 // Workspace bytes for a search of half sizes (na, nb); nb < 0 = one half only.
-uint64_t plan_job(int na, int nb, JobPlan &P, uint64_t kcap);
+// `batch`: the search runs beside many others in one launch per stage.
+uint64_t plan_job(int na, int nb, JobPlan &P, uint64_t kcap, bool batch = false);
 // Lay the job out at ws and fill its kernel arguments (B' weights negated).
 void build_job(JobPlan &P, char *ws, const uint64_t *wa, const uint64_t *wb, uint64_t t_lo, uint64_t t_hi,
                uint64_t *out, uint64_t *out_count, uint64_t cap, dev::JobArgs &J);

@@ -115,7 +115,13 @@ __device__ __forceinline__ void emit_pair(const JobArgs &J, uint64_t a, uint64_t
 // A launch serves one search (MULTI = false: the job is the kernel argument)
 // or every search of a batch (MULTI = true: M.jobs in device memory and, per
 // stage, M.bases[stage][0..njobs] the first block of each job, so block x
-// belongs to job j with bases[j] <= x < bases[j+1]).
+// belongs to the last job j with bases[j] <= x).  The stage's table in
+// M.groups names the jobs of blocks g * PICK_GRP and (g + 1) * PICK_GRP, which
+// bound x's job, so the search among bases takes a step or two instead of
+// log2(njobs) dependent loads.  The job's arguments are read through the
+// constant address space (no kernel writes them): scalar loads that stay
+// valid across barriers, and the pointers in them are known to be global, as
+// they are when the job is the kernel argument.
 template <bool MULTI>
 __device__ __forceinline__ bool pick(const JobArgs &arg, const Multi &M, int stage, const JobArgs *&J, uint32_t &bx) {
     if (!MULTI) {
@@ -124,15 +130,16 @@ __device__ __forceinline__ bool pick(const JobArgs &arg, const Multi &M, int sta
         return true;
     }
     const uint32_t *base = M.bases + (size_t)stage * (M.njobs + 1);
+    const uint32_t *grp = M.groups + M.gofs[stage];
     const uint32_t x = blockIdx.x;
     if (x >= base[M.njobs]) return false;
-    int lo = 0, hi = M.njobs - 1;  // last j with base[j] <= x
+    int lo = (int)grp[x / PICK_GRP], hi = (int)grp[x / PICK_GRP + 1];  // lo <= job(x) <= hi
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (base[mid] <= x) lo = mid;
         else hi = mid - 1;
     }
-    J = M.jobs + lo;
+    J = (const JobArgs *)((const __attribute__((address_space(4))) JobArgs *)M.jobs + lo);
     bx = x - base[lo];
     return true;
 }
@@ -1268,11 +1275,14 @@ Tune get_tune(int lg) {
     return (lg >= 0 && lg <= MAX_HALF) ? g_tune[lg] : Tune{-1, -1, 0.0};
 }
 
-static void plan_bits(uint64_t nmax, int &B1, int &B2) {
+static void plan_bits(uint64_t nmax, bool batch, int &B1, int &B2) {
     int lg = 0;
     while ((1ull << lg) < nmax) ++lg;
     const Tune tn = get_tune(lg);
-    const int sub = (tn.sub_log >= SUB_LOG_MIN && tn.sub_log <= SUB_LOG) ? tn.sub_log : SUB_LOG;
+    // The table is timed on one search at a time, where smaller sub-buckets
+    // (more workgroups) fill the chip; a batch fills it with its many
+    // searches, so it takes the largest sub-buckets (fewest workgroups).
+    const int sub = batch ? SUB_LOG : (tn.sub_log >= SUB_LOG_MIN && tn.sub_log <= SUB_LOG) ? tn.sub_log : SUB_LOG;
     int LB = lg > sub ? lg - sub : 0;
     if (LB > MAXB1_LOG + MAXB2_LOG) LB = MAXB1_LOG + MAXB2_LOG;
     if (tn.b1 >= 0) {
@@ -1328,7 +1338,7 @@ static uint64_t layout(JobPlan &P, char *base) {
     return off;
 }
 
-uint64_t plan_job(int na, int nb, JobPlan &P, uint64_t kcap) {
+uint64_t plan_job(int na, int nb, JobPlan &P, uint64_t kcap, bool batch) {
     P = JobPlan();
     P.kcap = kcap;
     P.nhalves = nb >= 0 ? 2 : 1;
@@ -1338,7 +1348,7 @@ uint64_t plan_job(int na, int nb, JobPlan &P, uint64_t kcap) {
         plan_half(nb, P.h[1]);
         nmax = std::max(nmax, P.h[1].N);
     }
-    plan_bits(nmax, P.B1, P.B2);
+    plan_bits(nmax, batch, P.B1, P.B2);
     return layout(P, nullptr);
 }
 
@@ -1469,7 +1479,7 @@ rfr_status enqueue_recombine(const uint64_t *w, int n, uint64_t t_lo, uint64_t t
     for (int i = 0; i < nb; ++i) wneg[i] = 0 - w[na + i];
     uint32_t grids[NSTAGES];
     stage_blocks(P, grids);
-    Multi M{nullptr, nullptr, 0};
+    Multi M{};
     const uint64_t nchunks = 1ull << c;
     for (uint64_t t = 0; t < nchunks; ++t) {
         JobArgs J;
@@ -1526,7 +1536,7 @@ rfr_status enqueue_expand(const uint64_t *w, int m, int negate, void *ws, size_t
     J.kcap = 1;
     uint32_t grids[NSTAGES];
     stage_blocks(P, grids);
-    Multi M{nullptr, nullptr, 0};
+    Multi M{};
     if (launch_all<false>(J, M, grids, 1, P.B1, P.B2, false, sorted, st, nullptr) != hipSuccess) {
         err = "kernel launch failed";
         return RFR_EDEVICE;
@@ -1545,18 +1555,47 @@ void MultiLaunch::add(const JobPlan &P, const JobArgs &J) {
     maxB2 = std::max(maxB2, P.B2);
 }
 
-size_t MultiLaunch::bases_bytes() const { return (size_t)NSTAGES * (jobs.size() + 1) * 4; }
+// Entries of each stage's block -> job table (see pick()).
+static uint32_t group_entries(uint32_t grid) { return (grid + PICK_GRP - 1) / PICK_GRP + 1; }
+
+size_t MultiLaunch::bases_bytes() const {
+    size_t n = (size_t)NSTAGES * (jobs.size() + 1);
+    for (int s = 0; s < NSTAGES; ++s) n += group_entries(bases.empty() ? 0 : bases[s].back());
+    return n * 4;
+}
 
 void MultiLaunch::pack_bases(uint32_t *dst) const {
     const size_t nj = jobs.size();
     for (int s = 0; s < NSTAGES; ++s)
         for (size_t j = 0; j <= nj; ++j) dst[s * (nj + 1) + j] = bases.empty() ? 0 : bases[s][j];
+    uint32_t *g = dst + (size_t)NSTAGES * (nj + 1);
+    for (int s = 0; s < NSTAGES; ++s) {
+        const uint32_t grid = bases.empty() ? 0 : bases[s].back();
+        const uint32_t ne = group_entries(grid);
+        size_t j = 0;  // last job whose first block is <= x
+        for (uint32_t e = 0; e + 1 < ne; ++e) {
+            const uint64_t x = (uint64_t)e * PICK_GRP;
+            while (j + 1 < nj && bases[s][j + 1] <= x) ++j;
+            g[e] = (uint32_t)j;
+        }
+        g[ne - 1] = nj ? (uint32_t)(nj - 1) : 0;
+        g += ne;
+    }
 }
 
 hipError_t MultiLaunch::launch(const JobArgs *jobs_dev, const uint32_t *bases_dev, hipStream_t st,
                                StageEvents *ev) const {
     if (jobs.empty()) return hipSuccess;
-    Multi M{jobs_dev, bases_dev, (int)jobs.size()};
+    Multi M{};
+    M.jobs = jobs_dev;
+    M.bases = bases_dev;
+    M.njobs = (int)jobs.size();
+    M.groups = bases_dev + (size_t)NSTAGES * (jobs.size() + 1);
+    uint32_t off = 0;
+    for (int s = 0; s < NSTAGES; ++s) {
+        M.gofs[s] = off;
+        off += group_entries(bases[s].back());
+    }
     uint32_t grids[NSTAGES];
     for (int s = 0; s < NSTAGES; ++s) grids[s] = bases[s].back();
     JobArgs dummy{};

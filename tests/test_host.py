@@ -165,3 +165,44 @@ def test_weights_rounding_tight_against_oracle(R):
         for a, b in zip(got["w"], ow):
             worst = max(worst, abs(_signed(a - b)))
     assert worst <= 4, worst
+
+
+def test_results_pack_flattens_in_order(R):
+    # host-only ABI call on results laid out by hand: two results, a null
+    # (failed) entry between them, then a size check that writes nothing
+    import ctypes as C
+    import numpy as np
+    made = []
+
+    def result(content, factors):
+        degs = (C.c_int32 * max(len(factors), 1))(*[len(f) - 1 for f in factors])
+        co = (C.c_int64 * max(sum(len(f) for f in factors), 1))(*[c for f in factors for c in f])
+        r = R.Result(content=content, nfactors=len(factors), degrees=C.cast(degs, C.POINTER(C.c_int32)),
+                     coeffs=C.cast(co, C.POINTER(C.c_int64)))
+        made.extend([degs, co, r])
+        return C.pointer(r)
+
+    a = [(1, 1), (-3, 0, 2), (5, 4, 0, 1)]
+    b = [(0, 1)]
+    outs = (C.POINTER(R.Result) * 3)(result(-6, a), None, result(2, b))
+    sts = (C.c_int * 3)(0, -4, 0)
+    L = R.lib()
+    nd, nc = C.c_size_t(), C.c_size_t()
+    assert L.rfr_results_pack(outs, 3, None, None, None, 0, None, 0, C.byref(nd), C.byref(nc)) == 0
+    assert (nd.value, nc.value) == (4, 2 + 3 + 4 + 2)
+    small = np.zeros(4, dtype=np.int64)
+    assert L.rfr_results_pack(outs, 3, small.ctypes.data, small.ctypes.data, small.ctypes.data, 4,
+                              small.ctypes.data, 3, C.byref(nd), C.byref(nc)) == -1
+    assert not small.any()
+    res = R._unpack_many(outs, sts, 3)
+    assert res[0] == (-6, [tuple(f) for f in a])
+    assert isinstance(res[1], R.RFRError)
+    assert res[2] == (2, [tuple(f) for f in b])
+
+
+def test_flatten_batch_inputs(R):
+    degs, flat = R._flatten([[1, 2, 3], [4, 5], [6, 7, 8, 9]])
+    assert degs.tolist() == [2, 1, 3]
+    assert flat.tolist() == list(range(1, 10))
+    with pytest.raises(OverflowError):
+        R._flatten([[1, 1 << 63]])
