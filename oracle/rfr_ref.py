@@ -27,6 +27,10 @@ What it computes (paper sections in brackets):
                      a_d * q and exact trial division.
 * ``factor``         FACTOR end to end, returning the irreducible
                      factorisation (the atoms of all divisors found).
+* ``squarefree``     Yun's square-free decomposition [Section 2: a
+                     polynomial that is not square-free is split into
+                     square-free parts first], and ``factor_general``: FACTOR
+                     on each part, factors repeated by multiplicity.
 
 Readings of the paper taken here (each also stated where it is used):
 
@@ -500,6 +504,94 @@ def atoms(n: int, confirmed: Dict[int, List[int]]) -> List[int]:
                 a &= t
         out.add(a)
     return sorted(out)
+
+
+# --------------------------------------------------------------------------
+# square-free decomposition (Section 2: Yun's algorithm ahead of FACTOR)
+# --------------------------------------------------------------------------
+
+def _derivative(p: Sequence[int]) -> List[int]:
+    return [i * int(p[i]) for i in range(1, len(p))] or [0]
+
+
+def _is_zero(p: Sequence[int]) -> bool:
+    return all(int(c) == 0 for c in p)
+
+
+def _gcd_z(f: Sequence[int], g: Sequence[int]) -> List[int]:
+    """Primitive gcd (lc > 0) of two integer polynomials; sympy's polynomial
+    gcd serves as the library step."""
+    import sympy
+    x = sympy.Symbol("x")
+    if _is_zero(g):
+        return primitive(f)
+    if _is_zero(f):
+        return primitive(g)
+    F = sympy.Poly(list(reversed([int(c) for c in f])), x)
+    G = sympy.Poly(list(reversed([int(c) for c in g])), x)
+    h = sympy.gcd(F, G)
+    return primitive([int(c) for c in reversed(h.all_coeffs())])
+
+
+def _sub(a: Sequence[int], b: Sequence[int]) -> List[int]:
+    n = max(len(a), len(b))
+    a = list(a) + [0] * (n - len(a))
+    b = list(b) + [0] * (n - len(b))
+    return _trim([int(x) - int(y) for x, y in zip(a, b)])
+
+
+def squarefree(coeffs: Sequence[int]) -> Tuple[int, List[Tuple[Tuple[int, ...], int]]]:
+    """Square-free decomposition p = content * prod part**mult.
+
+    Yun's algorithm over Z with primitive associates (every quotient below is
+    exact): with f the primitive part of p without its powers of x,
+    a0 = gcd(f, f'), b = f / a0, c = f' / a0, d = c - b'; then repeatedly
+    a = gcd(b, d) is the part of the next multiplicity, b <- b / a,
+    c <- d / a, d <- c - b', until b is constant.  A power x**k is the part x
+    with multiplicity k.  Parts are primitive with lc > 0, sorted by
+    (multiplicity, degree, coefficients).
+    """
+    cont, k, f = normalise(coeffs)
+    parts: List[Tuple[Tuple[int, ...], int]] = []
+    if k:
+        parts.append(((0, 1), k))
+    if len(f) > 1:
+        fd = _derivative(f)
+        a0 = _gcd_z(f, fd)
+        b = exact_divide(f, a0)
+        c = exact_divide(fd, a0)
+        if b is None or c is None:
+            raise OracleError("inexact division in the square-free decomposition")
+        d = _sub(c, _derivative(b))
+        mult = 1
+        while len(b) > 1:
+            a = primitive(b) if _is_zero(d) else _gcd_z(b, d)
+            if len(a) > 1:
+                parts.append((tuple(a), mult))
+            b2 = exact_divide(b, a)
+            c2 = [0] if _is_zero(d) else exact_divide(d, a)
+            if b2 is None or c2 is None:
+                raise OracleError("inexact division in the square-free decomposition")
+            b = _trim(b2)
+            d = _sub(c2, _derivative(b))
+            mult += 1
+    parts.sort(key=lambda pm: (pm[1], len(pm[0]), pm[0]))
+    return cont, parts
+
+
+def factor_general(coeffs: Sequence[int]) -> Tuple[int, List[Tuple[int, ...]]]:
+    """Irreducible factorisation of any nonzero p of degree >= 1: FACTOR on
+    every square-free part (Section 2), each factor listed as often as its
+    multiplicity, in the canonical order."""
+    cont, parts = squarefree(coeffs)
+    facs: List[List[int]] = []
+    for part, mult in parts:
+        c1, fs = factor(list(part))
+        if c1 != 1:
+            raise OracleError("square-free part is not primitive")
+        for f in fs:
+            facs.extend([list(f)] * mult)
+    return cont, canonical(facs)
 
 
 def canonical(factors: List[List[int]]) -> List[Tuple[int, ...]]:

@@ -265,3 +265,83 @@ def test_element_count_near_kac_estimate():
         assert 30 <= len(ts) <= 60        # d/2 <= n <= d (Section 1)
     est = 60 / 2 + math.log(60) / math.pi
     assert abs(np.mean(ns) - est) < 3
+
+
+# ---- square-free decomposition (Section 2: Yun's algorithm ahead of FACTOR)
+
+def sympy_sqf(coeffs):
+    """(content, [(part, mult)]) from sympy.sqf_list, parts primitive with lc > 0."""
+    c, fl = sympy.sqf_list(sympy.Poly(list(reversed([int(v) for v in coeffs])), X))
+    c = int(c)
+    parts = []
+    for f, m in fl:
+        cs = [int(v) for v in reversed(f.all_coeffs())]
+        g = R.content(cs)
+        if cs[-1] < 0:
+            g = -g
+        cs = [v // g for v in cs]
+        c *= g ** m
+        parts.append((tuple(cs), m))
+    # sympy keeps a power of x inside the part of its multiplicity; split it off
+    out = []
+    for cs, m in parts:
+        k = 0
+        while cs[k] == 0:
+            k += 1
+        if k:
+            out.append(((0, 1), m))
+        if len(cs) - k > 1:
+            out.append((tuple(cs[k:]), m))
+    merged = {}
+    for cs, m in out:
+        if cs == (0, 1):
+            merged[(cs, "x")] = merged.get((cs, "x"), 0) + m
+        else:
+            merged[(cs, m)] = m
+    res = [(cs, m) for (cs, _), m in merged.items()]
+    res.sort(key=lambda pm: (pm[1], len(pm[0]), pm[0]))
+    return c, res
+
+
+def test_squarefree_matches_sympy_sqf_list():
+    cases = [w.coeffs for w in W.config_repeated()]
+    cases += [[0, 0, 0, 1, 1], [1, 2, 1], [-4, 0, 4], [0, 0, 2], [6, -5, 1]]
+    for p in cases:
+        assert R.squarefree(p) == sympy_sqf(p), p
+
+
+def test_squarefree_recovers_planted_multiplicities():
+    # the drawn factors of these seeds are square-free and pairwise coprime,
+    # so the part of multiplicity m is the product of those drawn m times
+    for w in W.config_repeated():
+        cont, parts = R.squarefree(w.coeffs)
+        counts = {}
+        for f in w.planted:
+            counts[tuple(f)] = counts.get(tuple(f), 0) + 1
+        k = counts.pop((0, 1), 0)
+        want = {}
+        for f, m in counts.items():
+            want[m] = R.poly_mul_exact(want.get(m, [1]), list(f))
+        want = {m: R.primitive(prod) for m, prod in want.items()}
+        got = {m: list(part) for part, m in parts if part != (0, 1)}
+        assert got == want, w.seed
+        assert [m for part, m in parts if part == (0, 1)] == ([k] if k else []), w.seed
+        # reconstruction: content * prod part**mult == p
+        q = [cont]
+        for part, m in parts:
+            for _ in range(m):
+                q = R.poly_mul_exact(q, list(part))
+        assert q == [int(c) for c in w.coeffs], w.seed
+
+
+def test_squarefree_of_squarefree_input_is_itself():
+    for w in [W.config_small()] + W.config_mid(4):
+        cont, k, prim = R.normalise(w.coeffs)
+        cont2, parts = R.squarefree(w.coeffs)
+        assert cont2 == cont
+        assert parts == ([((0, 1), k)] if k else []) + [(tuple(prim), 1)]
+
+
+def test_factor_general_matches_sympy_factor_list():
+    for w in W.config_repeated()[:12]:
+        assert R.factor_general(w.coeffs) == sympy_factor(w.coeffs), w.seed

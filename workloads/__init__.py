@@ -175,3 +175,36 @@ def config_stream(count: int, rate_per_s: float, seed: int = 5000,
             w = Workload(rand_poly(sub, d, lo, hi), seed * 100003 + k, "random")
         out.append(Request(t, w))
     return out
+
+
+def config_repeated(count: int = 24, base_seed: int = 6000, lo: int = -20, hi: int = 20) -> List[Workload]:
+    """Polynomials that are not square-free: p = c * x**k * prod_m f_m**m.
+
+    For each seed: 1-3 random factors (degree 1-8 each, coefficients in
+    [lo, hi]) with multiplicities drawn from 1..3 (at least one above 1),
+    a power x**k with k in 0..2, and a content c in [1, 3] with a random
+    sign.  ``planted`` lists every drawn factor once per multiplicity (x as
+    [0, 1]); the content is the product's, not part of ``planted``.
+    """
+    out = []
+    for i in range(count):
+        seed = base_seed + i
+        rng = _rng(seed)
+        nf = int(rng.integers(1, 4))
+        mults = [int(rng.integers(1, 4)) for _ in range(nf)]
+        if max(mults) == 1:
+            mults[int(rng.integers(0, nf))] = int(rng.integers(2, 4))
+        k = int(rng.integers(0, 3))
+        c = int(rng.integers(1, 4)) * (1 if rng.uniform() < 0.5 else -1)
+        p = [c]
+        planted = []
+        for m in mults:
+            f = rand_poly(rng, int(rng.integers(1, 9)), lo, hi)
+            for _ in range(m):
+                p = poly_mul(p, f)
+                planted.append(f)
+        for _ in range(k):
+            p = poly_mul(p, [0, 1])
+            planted.append([0, 1])
+        out.append(Workload(p, seed, "repeated", planted))
+    return out
