@@ -1,7 +1,7 @@
 /*
  * rfr.h -- C ABI of the MI355X Real-Factors-Recombination (RFR) library.
  *
- * The library factors a square-free integer polynomial p(x) into irreducible
+ * The library factors an integer polynomial p(x) into irreducible
  * factors over Z by the method of Iravanian, "Integer Polynomial Factorization
  * by Recombination of Real Factors" (arXiv 2410.15880):
  *
@@ -15,6 +15,9 @@
  *   4. every candidate pattern is confirmed by exact trial division on the
  *      host (Section 2, Algorithm FACTOR), and the irreducible factors are the
  *      atoms of the divisors found.
+ * The method needs a square-free p (Section 2); a p with repeated factors is
+ * first split into square-free parts by Yun's algorithm and each part is
+ * factored in turn (rfr_squarefree exposes that decomposition).
  *
  * Conventions for every entry point:
  *   - Polynomials are int64 coefficient arrays in ascending order:
@@ -41,7 +44,9 @@ extern "C" {
 typedef enum rfr_status {
     RFR_OK = 0,
     RFR_EINVAL = -1,       /* bad argument: degree < 1, zero leading coeff, NULL */
-    RFR_ENOTSQFREE = -2,   /* p has a repeated factor (the method needs square-free p) */
+    RFR_ENOTSQFREE = -2,   /* p has a repeated factor: returned by the host-stage calls
+                              (rfr_weights, rfr_prepare_batch); the factoring calls
+                              decompose such p instead (rfr_squarefree) */
     RFR_ENOMEM = -3,       /* device or host allocation failed / over the memory budget */
     RFR_EPRECISION = -4,   /* roots could not be separated or the accept window is too wide */
     RFR_EOVERFLOW = -5,    /* a coefficient or element count exceeds the supported range */
@@ -62,7 +67,9 @@ typedef struct rfr_ctx rfr_ctx;
  * coeffs[off_k .. off_k + degrees[k]] (ascending), off_k = sum_{i<k}(degrees[i]+1).
  * Factors are primitive, irreducible over Z, with positive leading
  * coefficient, sorted by (degree, coefficient tuple in ascending-power order).
- * A factor x is reported when p(0) = 0.
+ * A factor x is reported when p(0) = 0.  A factor of multiplicity m appears
+ * m times (only when p is not square-free; the counters then sum over its
+ * square-free parts and t_lo/t_hi are those of the part with most elements).
  */
 typedef struct rfr_result {
     int64_t content;           /* signed integer content of p */
@@ -98,8 +105,10 @@ rfr_status rfr_set_candidate_cap(rfr_ctx *ctx, uint64_t cap);
 /* Factor one polynomial (Algorithm FACTOR, Section 2).
  * coeffs: host array [degree + 1]; degree in [1, RFR_MAX_DEGREE].
  * The search runs on the context's device; the call blocks until done.
- * Errors: RFR_EINVAL, RFR_ENOTSQFREE, RFR_EPRECISION, RFR_EOVERFLOW,
- * RFR_ECANDIDATES, RFR_ENOMEM, RFR_EDEVICE. */
+ * A p that is not square-free is factored through its square-free parts
+ * (rfr_squarefree), each by the square-free path.
+ * Errors: RFR_EINVAL, RFR_EPRECISION, RFR_EOVERFLOW, RFR_ECANDIDATES,
+ * RFR_ENOMEM, RFR_EDEVICE. */
 rfr_status rfr_factor(rfr_ctx *ctx, const int64_t *coeffs, int degree, rfr_result **out);
 
 /* ------------------------------------------------------------------ batched */
@@ -173,6 +182,20 @@ rfr_status rfr_autotune(rfr_ctx *ctx, int lg_lo, int lg_hi, const char *path_out
  * searches. */
 rfr_status rfr_load_tuning(const char *path);
 
+/* ------------------------------------------------------------------ square-free parts */
+
+/* Square-free decomposition (Section 2: Yun's algorithm, the step that lets
+ * the method take any p): p = content * prod_j part_j ^ mult_j with every part
+ * primitive, square-free, lc > 0 and pairwise coprime; a power of x is the
+ * part x.  Parts are sorted by (mult, degree, coefficients).  Host only.
+ * parts_out receives the parts' coefficients back to back (ascending;
+ * capacity 2 * degree + 2 suffices), degrees_out and mult_out one entry per
+ * part (capacity degree + 1), *nparts the number of parts.  A square-free p
+ * gives its primitive part (and x) with multiplicity 1.  Errors: RFR_EINVAL,
+ * RFR_EOVERFLOW (a gcd or quotient leaves int64). */
+rfr_status rfr_squarefree(const int64_t *coeffs, int degree, int64_t *content, int64_t *parts_out,
+                          int32_t *degrees_out, int32_t *mult_out, int *nparts);
+
 /* ------------------------------------------------------------------ results */
 
 void rfr_result_free(rfr_result *res);
@@ -199,7 +222,8 @@ const char *rfr_last_error(void);
  * w_out: host array of at least `degree` entries, receives n weights in
  * canonical element order (real roots ascending, then conjugate pairs by
  * (Re, Im)); n_out, n_real_out, t_lo, t_hi receive n, r and the accept
- * window.  Runs on the host only. */
+ * window.  Runs on the host only.  RFR_ENOTSQFREE for a p with a repeated
+ * factor (its elements are not defined; see rfr_squarefree). */
 rfr_status rfr_weights(const int64_t *coeffs, int degree, uint64_t *w_out, int32_t *n_out,
                        int32_t *n_real_out, uint64_t *t_lo, uint64_t *t_hi);
 

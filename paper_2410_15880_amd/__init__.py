@@ -32,6 +32,7 @@ EXPORTS = [
     "rfr_recombine_dev", "rfr_expand_workspace_bytes", "rfr_expand_dev",
     "rfr_profile", "rfr_profile_read", "rfr_recombine_min_workspace_bytes",
     "rfr_autotune", "rfr_load_tuning", "rfr_prepare_batch", "rfr_results_pack", "rfr_results_free",
+    "rfr_squarefree",
 ]
 
 
@@ -88,6 +89,8 @@ def lib():
         "rfr_result_free": ([RP], None),
         "rfr_results_pack": ([C.POINTER(RP), C.c_int, P, P, P, sz, P, sz, C.POINTER(sz), C.POINTER(sz)], C.c_int),
         "rfr_results_free": ([C.POINTER(RP), C.c_int], None),
+        "rfr_squarefree": ([C.POINTER(i64), C.c_int, C.POINTER(i64), C.POINTER(i64), C.POINTER(i32),
+                            C.POINTER(i32), C.POINTER(C.c_int)], C.c_int),
         "rfr_strerror": ([C.c_int], C.c_char_p),
         "rfr_last_error": ([], C.c_char_p),
         "rfr_weights": ([C.POINTER(i64), C.c_int, C.POINTER(u64), C.POINTER(i32), C.POINTER(i32),
@@ -142,6 +145,25 @@ def _unpack(rp) -> dict:
            "ms_search": r.ms_search, "ms_confirm": r.ms_confirm}
     lib().rfr_result_free(rp)
     return out
+
+
+def squarefree(coeffs: Sequence[int]) -> Tuple[int, List[Tuple[Tuple[int, ...], int]]]:
+    """Square-free decomposition (host, Yun): (content, [(part, multiplicity)])
+    with p = content * prod part**multiplicity, parts sorted by (multiplicity,
+    degree, coefficients)."""
+    d = len(coeffs) - 1
+    cs = _i64(coeffs)
+    cont = C.c_int64()
+    parts = (C.c_int64 * (2 * max(d, 0) + 2))()
+    degs = (C.c_int32 * (max(d, 0) + 1))()
+    mult = (C.c_int32 * (max(d, 0) + 1))()
+    np_ = C.c_int()
+    _check(lib().rfr_squarefree(cs, d, C.byref(cont), parts, degs, mult, C.byref(np_)))
+    out, k = [], 0
+    for j in range(np_.value):
+        out.append((tuple(parts[k:k + degs[j] + 1]), int(mult[j])))
+        k += degs[j] + 1
+    return int(cont.value), out
 
 
 def _flatten(polys: Sequence[Sequence[int]]):

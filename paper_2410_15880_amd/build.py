@@ -41,6 +41,7 @@ UNITS = [
     ("rfr_batch.cpp", "hip"),
     ("rfr_serve.cpp", "hiphost"),
     ("rfr_tune.cpp", "hiphost"),
+    ("rfr_sqf.cpp", "hiphost"),
 ]
 
 

@@ -298,7 +298,11 @@ rfr_status rfr_factor(rfr_ctx *ctx, const int64_t *coeffs, int degree, rfr_resul
     if (!ctx || !out) return fail(RFR_EINVAL, "ctx/out is NULL");
     *out = nullptr;
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(RFR_EDEVICE, "hipSetDevice failed");
-    return factor_on_slot(ctx, ctx->main, coeffs, degree, out);
+    rfr_status st = factor_on_slot(ctx, ctx->main, coeffs, degree, out);
+    if (st != RFR_ENOTSQFREE) return st;
+    return factor_sqf_route(coeffs, degree, [&](const int64_t *c, int d, rfr_result **o) {
+        return factor_on_slot(ctx, ctx->main, c, d, o);
+    }, out);
 }
 
 void rfr_result_free(rfr_result *res) { std::free(res); }

@@ -529,6 +529,15 @@ extern "C" rfr_status rfr_factor_batch(rfr_ctx *ctx, int count, const int64_t *c
             }
         });
     for (auto &t : pool) t.join();
+    // polynomials that are not square-free: their square-free parts through
+    // the plain path, one after another (the batch's device work is done)
+    for (int i = 0; i < count; ++i) {
+        if (status[i] != RFR_ENOTSQFREE) continue;
+        status[i] = factor_sqf_route(coeffs + off[i], degrees[i], [&](const int64_t *c, int d, rfr_result **o) {
+            return factor_on_slot(ctx, ctx->main, c, d, o);
+        }, &out[i]);
+        err[i] = status[i] == RFR_OK ? std::string() : g_last_error;
+    }
     for (int i = 0; i < count; ++i)
         if (status[i] != RFR_OK && !err[i].empty()) g_last_error = err[i];
     return RFR_OK;

@@ -7,6 +7,7 @@
 #include <atomic>
 #include <condition_variable>
 #include <deque>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -99,6 +100,17 @@ void rootbuf_free(RootBuf &b);
 // when the device roots fail the disc checks.
 rfr_status prepare_dev(RootBuf &b, const int64_t *coeffs, int degree, Prepared &P, std::string &err);
 rfr_status factor_on_slot(rfr_ctx *ctx, Slot &s, const int64_t *coeffs, int degree, rfr_result **out);
+
+// Square-free decomposition (Yun): p = content * prod parts[j].first ^ parts[j].second,
+// parts primitive, square-free, lc > 0, pairwise coprime, sorted by (multiplicity,
+// degree, coefficients); a factor x is its own part.
+rfr_status squarefree_decompose(const int64_t *coeffs, int degree, int64_t &content,
+                                std::vector<std::pair<std::vector<int64_t>, int>> &parts, std::string &err);
+// Factorisation of a polynomial the square-free path rejected: every
+// square-free part goes through `one` (the square-free path), its factors are
+// listed by multiplicity.
+using FactorOne = std::function<rfr_status(const int64_t *coeffs, int degree, rfr_result **out)>;
+rfr_status factor_sqf_route(const int64_t *coeffs, int degree, const FactorOne &one, rfr_result **out);
 void batch_release(rfr_ctx *ctx);
 StageEvents *profile_events(rfr_ctx *ctx, int k);
 void profile_collect(rfr_ctx *ctx, int k, int n);

@@ -89,14 +89,16 @@ static void release_slot(rfr_ctx *ctx, Slot *s) {
     ctx->cv_slot.notify_all();
 }
 
-static void serve_one(rfr_ctx *ctx, RootBuf &rb, Request *r) {
+// The square-free path for one polynomial: roots on this worker's stream,
+// admission to a device slot, search, confirmation.
+static rfr_status serve_poly(rfr_ctx *ctx, RootBuf &rb, const int64_t *coeffs, int degree, rfr_result **out) {
     double t0 = now_ms();
     Prepared P;
     std::string err;
     Factored F;
     std::vector<Pat> cands;
     rfr_result *res = nullptr;
-    rfr_status st = prepare_dev(rb, r->coeffs.data(), (int)r->coeffs.size() - 1, P, err);
+    rfr_status st = prepare_dev(rb, coeffs, degree, P, err);
     if (st != RFR_OK) st = fail(st, err);
     double t1 = now_ms(), t2 = t1;
     if (st == RFR_OK && P.n <= 1) {
@@ -132,6 +134,18 @@ static void serve_one(rfr_ctx *ctx, RootBuf &rb, Request *r) {
             res->ms_confirm = now_ms() - t2;
         }
     }
+    *out = res;
+    return st;
+}
+
+static void serve_one(rfr_ctx *ctx, RootBuf &rb, Request *r) {
+    const int degree = (int)r->coeffs.size() - 1;
+    rfr_result *res = nullptr;
+    rfr_status st = serve_poly(ctx, rb, r->coeffs.data(), degree, &res);
+    if (st == RFR_ENOTSQFREE)
+        st = factor_sqf_route(r->coeffs.data(), degree, [&](const int64_t *c, int d, rfr_result **o) {
+            return serve_poly(ctx, rb, c, d, o);
+        }, &res);
     std::lock_guard<std::mutex> lk(ctx->mu);
     r->status = st;
     r->result = res;

@@ -52,17 +52,35 @@ def test_batch_full_config_equals_plain(R):
 
 def test_batch_mixed_sizes_and_errors(R):
     polys = [[6, -5, 1], [1, -2, 1], [3, 7], W.config_small().coeffs] + [w.coeffs for w in W.config_mid()[:4]]
+    polys += [[0, 0, 1], [1, 0, 0, 0, 0, 2]]
     with R.Context(0) as ctx:
         got = ctx.factor_batch(polys)
-        assert isinstance(got[1], R.RFRError) and got[1].name == "RFR_ENOTSQFREE"
+        assert got[1] == (1, [(-1, 1), (-1, 1)])  # (x - 1)^2 through its square-free part
+        assert got[-2] == (1, [(0, 1), (0, 1)])
         for p, r in zip(polys, got):
-            if p == [1, -2, 1]:
-                continue
             assert r == ctx.factor(p)
+
+
+def test_batch_repeated_factors_match_oracle(R):
+    # inputs that are not square-free, mixed with square-free ones, in one batch
+    from oracle import rfr_ref as O
+    rep = W.config_repeated(24)
+    mix = [w.coeffs for w in W.config_batch(64, base_seed=9000)]
+    polys = [c for pair in zip([w.coeffs for w in rep], mix) for c in pair] + mix[len(rep):]
+    say("batch with repeated factors", len(polys))
+    with R.Context(0) as ctx:
+        got = ctx.factor_batch(polys)
+        for p, r in zip(polys, got):
+            assert r == ctx.factor(p)
+    for w in rep:
+        assert got[2 * rep.index(w)] == O.factor_general(w.coeffs), w.seed
 
 
 def test_served_alone_equals_in_mix(R):
     reqs = W.config_stream(48, rate_per_s=400.0, dcap=96)
+    # a few requests with repeated factors ride in the same stream
+    for i, w in enumerate(W.config_repeated(6)):
+        reqs.insert(4 + 7 * i, W.Request(reqs[4 + 7 * i].t_arrive, w))
     say("serving", len(reqs))
     with R.Context(0) as ctx:
         alone = [ctx.factor(r.work.coeffs) for r in reqs]

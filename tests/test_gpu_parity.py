@@ -146,10 +146,27 @@ def test_textbook_and_errors(R, ctx):
     for k in range(1, 9):
         p = O.poly_mul_exact(p, [-k, 1])
     assert ctx.factor(p) == O.factor(p)
-    for bad, name in [([1, -2, 1], "RFR_ENOTSQFREE"), ([0, 0, 1], "RFR_ENOTSQFREE"), ([5], "RFR_EINVAL")]:
+    # not square-free: factored through the square-free parts
+    assert ctx.factor([1, -2, 1]) == (1, [(-1, 1), (-1, 1)])
+    assert ctx.factor([0, 0, 1]) == (1, [(0, 1), (0, 1)])
+    for bad, name in [([5], "RFR_EINVAL"), ([1, 2, 0], "RFR_EINVAL")]:
         with pytest.raises(R.RFRError) as e:
             ctx.factor(bad)
         assert e.value.name == name
+
+
+def test_repeated_factors_match_oracle(ctx):
+    # Section 2: a polynomial with repeated factors is split by Yun's
+    # algorithm and each square-free part is factored
+    for w in W.config_repeated(24):
+        say("repeated", w.seed, w.degree)
+        assert ctx.factor(w.coeffs) == O.factor_general(w.coeffs), w.seed
+    # a repeated part large enough to need the device search: (f g)^2 with
+    # f, g of degree 20 (square-free part of degree 40, n about 20)
+    f, g = W.rand_poly(W._rng(7001), 20, -100, 100), W.rand_poly(W._rng(7002), 20, -100, 100)
+    p = O.poly_mul_exact(O.poly_mul_exact(f, g), O.poly_mul_exact(f, g))
+    say("repeated degree", len(p) - 1)
+    assert ctx.factor(p) == O.factor_general(p)
 
 
 def test_config_small_exact(ctx):

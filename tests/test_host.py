@@ -206,3 +206,40 @@ def test_flatten_batch_inputs(R):
     assert flat.tolist() == list(range(1, 10))
     with pytest.raises(OverflowError):
         R._flatten([[1, 1 << 63]])
+
+
+def test_squarefree_matches_oracle(R):
+    # the library's Yun decomposition (modular gcds) against the oracle's
+    # (sympy gcd as its library step) on seeded repeated-factor inputs
+    for w in W.config_repeated(60):
+        assert R.squarefree(w.coeffs) == O.squarefree(w.coeffs), w.seed
+
+
+@pytest.mark.parametrize("coeffs", [
+    [0, 0, 0, 1],                      # x^3
+    [0, 0, 0, 1, 1],                   # x^3 (x + 1)
+    [6, -5, 1],                        # square-free
+    [-4, 0, 4],                        # content 4, square-free part x^2 - 1
+    [1, -5, 10, -10, 5, -1],           # -(x - 1)^5
+    [-1, 0, 5, 0, -10, 0, 10, 0, -5, 0, 1],  # (x^2 - 1)^5
+    [4, 12, 13, 6, 1],                 # (x^2 + 3x + 2)^2
+])
+def test_squarefree_edge_cases(R, coeffs):
+    assert R.squarefree(coeffs) == O.squarefree(coeffs)
+
+
+def test_squarefree_rejects_bad_input(R):
+    with pytest.raises(R.RFRError):
+        R.squarefree([5])            # degree 0
+    with pytest.raises(R.RFRError):
+        R.squarefree([1, 2, 0])      # zero leading coefficient
+
+
+def test_squarefree_large_multiplicity(R):
+    # (3x - 2)^9 (x^2 + 1)^4: coefficients near 1e7, multiplicities up to 9
+    p = [1]
+    for _ in range(9):
+        p = O.poly_mul_exact(p, [-2, 3])
+    for _ in range(4):
+        p = O.poly_mul_exact(p, [1, 0, 1])
+    assert R.squarefree(p) == O.squarefree(p) == (1, [((1, 0, 1), 4), ((-2, 3), 9)])
