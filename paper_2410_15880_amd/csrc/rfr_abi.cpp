@@ -213,6 +213,7 @@ rfr_status factor_on_slot(rfr_ctx *ctx, Slot &s, const int64_t *coeffs, int degr
     Prepared P;
     std::string err;
     rfr_status st = prepare_dev(s.roots, coeffs, degree, P, err);
+    if (st == RFR_OK) st = peel_singletons(P, err);
     if (st != RFR_OK) return fail(st, err);
     double t1 = now_ms();
     Factored F;

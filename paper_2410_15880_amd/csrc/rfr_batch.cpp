@@ -308,6 +308,7 @@ extern "C" rfr_status rfr_factor_batch(rfr_ctx *ctx, int count, const int64_t *c
             for (int k; (k = next.fetch_add(1)) < count;) {
                 const int i = order[k];
                 if (st[i] == RFR_OK) (void)finish_or_host(P[i], rec[i], st[i], err[i]);
+                if (st[i] == RFR_OK) st[i] = peel_singletons(P[i], err[i]);
                 ready[i].store(1, std::memory_order_release);
             }
         });

@@ -466,11 +466,40 @@ static void host_roots(const Prepared &P, std::vector<RootOut> &ro) {
     }
 }
 
+// Weights (Section 3.3, Eq 18: w = floor(frac(a_d t) 2^64) with the elements
+// of the monic transform) and the accept window of the elements in P.
+static rfr_status weights_window(Prepared &P, std::string &err) {
+    const int d = (int)P.prim.size() - 1;
+    const dd a_d = dd_from_i64(P.prim[d]);
+    const double abs_ad = std::fabs((double)P.prim[d]);
+    double sum_delta = 0, sum_tau = 0;
+    P.w.clear();
+    for (int i = 0; i < P.n; ++i) {
+        const dd tau = i < P.r ? a_d * P.reals[i] : a_d * (P.pairs[i - P.r].re * 2.0);
+        P.w.push_back(weight_of(tau));
+        sum_delta += abs_ad * (i < P.r ? 1.0 : 2.0) * P.rad[i];
+        sum_tau += std::fabs(to_d(tau));
+    }
+    // Window (reading of Eq 19): a true k-element subset lands in (-k - E, E]
+    // mod 2^64 with E >= 2^64 * sum |a_d| delta_i; add the dd rounding of a_d t_i
+    // and one unit per weight for the floor of a rounded value.
+    double Ed = std::ldexp(2.0 * sum_delta + sum_tau * std::ldexp(1.0, -100), 64);
+    if (!(Ed < std::ldexp(1.0, 31))) {
+        err = "accept window too wide (roots not precise enough)";
+        return RFR_EPRECISION;
+    }
+    uint64_t E = (uint64_t)std::ceil(Ed) + 2 * (uint64_t)P.n + 2;
+    P.t_lo = (uint64_t)P.n + E;
+    P.t_hi = E;
+    return RFR_OK;
+}
+
 rfr_status finish_elements(Prepared &P, const RootOut *ro, std::string &err) {
     const int d = (int)P.prim.size() - 1;
     P.reals.clear();
     P.pairs.clear();
     P.w.clear();
+    P.rad.clear();
     std::vector<cdd> zc(d);
     std::vector<Disc> D(d);
     for (int i = 0; i < d; ++i) {
@@ -552,36 +581,15 @@ rfr_status finish_elements(Prepared &P, const RootOut *ro, std::string &err) {
         err = "too many elements";
         return RFR_EOVERFLOW;
     }
-    const dd a_d = dd_from_i64(P.prim[d]);
-    const double abs_ad = std::fabs((double)P.prim[d]);
-    double sum_delta = 0, sum_tau = 0;
     for (int k : orr) {
         P.reals.push_back(reals[k]);
-        dd tau = a_d * reals[k];
-        P.w.push_back(weight_of(tau));
-        sum_delta += abs_ad * rr[k];
-        sum_tau += std::fabs(to_d(tau));
+        P.rad.push_back(rr[k]);
     }
     for (int k : op) {
         P.pairs.push_back(up[k]);
-        dd t = up[k].re * 2.0;
-        dd tau = a_d * t;
-        P.w.push_back(weight_of(tau));
-        sum_delta += abs_ad * 2.0 * rpair[k];
-        sum_tau += std::fabs(to_d(tau));
+        P.rad.push_back(rpair[k]);
     }
-    // Window (reading of Eq 19): a true k-element subset lands in (-k - E, E]
-    // mod 2^64 with E >= 2^64 * sum |a_d| delta_i; add the dd rounding of a_d t_i
-    // and one unit per weight for the floor of a rounded value.
-    double Ed = std::ldexp(2.0 * sum_delta + sum_tau * std::ldexp(1.0, -100), 64);
-    if (!(Ed < std::ldexp(1.0, 31))) {
-        err = "accept window too wide (roots not precise enough)";
-        return RFR_EPRECISION;
-    }
-    uint64_t E = (uint64_t)std::ceil(Ed) + 2 * (uint64_t)P.n + 2;
-    P.t_lo = (uint64_t)P.n + E;
-    P.t_hi = E;
-    return RFR_OK;
+    return weights_window(P, err);
 }
 
 rfr_status prepare_elements(Prepared &P, std::string &err) {
@@ -672,6 +680,7 @@ void trivial_factor(const Prepared &P, Factored &out) {
     out.factors.clear();
     if (P.xpow == 1) out.factors.push_back({0, 1});
     if (P.prim.size() > 1) out.factors.push_back(P.prim);
+    for (auto &f : P.peeled) out.factors.push_back(f);
     std::sort(out.factors.begin(), out.factors.end(), canon_less);
 }
 
@@ -804,8 +813,97 @@ rfr_status confirm_and_factor(const Prepared &P, const std::vector<Pat> &cands, 
         }
         out.factors.push_back(it->second);
     }
+    for (auto &f : P.peeled) out.factors.push_back(f);
     std::sort(out.factors.begin(), out.factors.end(), canon_less);
     return RFR_OK;
+}
+
+// Does the root of the integer factor f (degree 1, or degree 2 with complex
+// roots) lie in element i's inclusion disc?  Only then is f that element's
+// factor (the discs are disjoint and hold one root each).
+static bool root_in_disc(const Prepared &P, int i, const std::vector<int64_t> &f) {
+    const double r = P.rad[i];
+    if (i < P.r) {
+        const dd g = dd_from_i64(f[1]), h = dd_from_i64(f[0]);
+        const dd res = g * P.reals[i] + h;  // g (u - root)
+        const double tol = std::fabs(to_d(g)) * r * (1 + 1e-9) +
+                           std::ldexp(std::fabs(to_d(g * P.reals[i])) + std::fabs(to_d(h)), -96);
+        return std::fabs(to_d(res)) <= tol;
+    }
+    if (f.size() != 3) return false;
+    for (int64_t c : f)
+        if (c > ((int64_t)1 << 60) || c < -((int64_t)1 << 60)) return false;  // keeps the discriminant in range
+    const i128 disc = (i128)4 * f[2] * f[0] - (i128)f[1] * f[1];
+    if (disc <= 0) return false;
+    const dd two_g = dd_from_i64(f[2]) * 2.0;
+    const dd re = -dd_from_i64(f[1]) / two_g;
+    // sqrt of disc in double-double: one Newton step from the double root
+    const double dd_hi = (double)disc;
+    const dd dv = dd_from_i64((int64_t)(disc >> 62)) * std::ldexp(1.0, 62) + dd_from_i64((int64_t)(disc & (((i128)1 << 62) - 1)));
+    double x0 = std::sqrt(dd_hi);
+    dd x = mkdd(x0);
+    x = x + (dv - x * x) / (x * 2.0);
+    const dd im = x / two_g;
+    const cdd &z = P.pairs[i - P.r];
+    const double dre = to_d(re - z.re), dim = to_d(im - z.im);
+    const double tol = r * (1 + 1e-9) + std::ldexp(std::fabs(to_d(z.re)) + std::fabs(to_d(z.im)), -96);
+    return std::hypot(dre, dim) <= tol;
+}
+
+rfr_status peel_singletons(Prepared &P, std::string &err) {
+    if (P.n < 2) return RFR_OK;
+    std::vector<char> gone(P.n, 0);
+    int npeeled = 0;
+    for (int i = 0; i < P.n; ++i) {
+        const int d = (int)P.prim.size() - 1;
+        if (d < 2) break;  // what is left is irreducible
+        const dd a_d = dd_from_i64(P.prim[d]);
+        std::vector<dd> q;
+        if (i < P.r) {
+            q = {a_d * P.reals[i] * -1.0, a_d};
+        } else {
+            const cdd &z = P.pairs[i - P.r];
+            const dd t = z.re * 2.0, s2 = z.re * z.re + z.im * z.im;
+            q = {a_d * s2, a_d * t * -1.0, a_d};
+        }
+        std::vector<int64_t> f(q.size());
+        bool ok = true;
+        for (size_t k = 0; k < q.size() && ok; ++k) ok = round_dd(q[k], f[k]);
+        if (!ok) continue;
+        make_primitive(f);
+        if (f.back() <= 0) continue;
+        // f's root must lie in this element's disc (else the rounding hit an
+        // integer by chance, or the root belongs to another element); only
+        // then is the exact division tried (an overflow there means no factor)
+        if (!root_in_disc(P, i, f)) continue;
+        std::vector<int64_t> g;
+        bool ovf = false;
+        if (!exact_div(P.prim, f, g, ovf) || g.back() <= 0) continue;
+        P.peeled.push_back(f);
+        P.prim = g;
+        gone[i] = 1;
+        ++npeeled;
+    }
+    if (!npeeled) return RFR_OK;
+    std::vector<dd> reals;
+    std::vector<cdd> pairs;
+    std::vector<double> rad;
+    for (int i = 0; i < P.n; ++i) {
+        if (gone[i]) continue;
+        if (i < P.r) reals.push_back(P.reals[i]);
+        else pairs.push_back(P.pairs[i - P.r]);
+        rad.push_back(P.rad[i]);
+    }
+    P.reals.swap(reals);
+    P.pairs.swap(pairs);
+    P.rad.swap(rad);
+    P.r = (int)P.reals.size();
+    P.n = P.r + (int)P.pairs.size();
+    if ((int)P.prim.size() - 1 != P.r + 2 * (int)P.pairs.size()) {
+        err = "degree mismatch after splitting off single-element factors";
+        return RFR_EPRECISION;
+    }
+    return weights_window(P, err);
 }
 
 }  // namespace rfr

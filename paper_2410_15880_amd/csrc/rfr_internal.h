@@ -47,6 +47,8 @@ struct Prepared {
     std::vector<cdd> pairs;       // c conjugate-pair representatives (Im > 0), by (Re, Im)
     std::vector<uint64_t> w;      // n weights, canonical element order
     uint64_t t_lo = 0, t_hi = 0;  // accept window
+    std::vector<double> rad;      // n inclusion radii (a pair: the larger of its two discs)
+    std::vector<std::vector<int64_t>> peeled;  // factors of single elements split off before the search
 };
 
 // One irreducible factor list with content (the result before ABI packing).
@@ -85,6 +87,13 @@ rfr_status confirm_and_factor(const Prepared &P, const std::vector<Pat> &cands, 
 
 // Trivial factorisation when no search is needed (n <= 1).
 void trivial_factor(const Prepared &P, Factored &out);
+// Single-element factors (a real root whose a_d (x - u) rounds to an integer
+// factor, a pair whose a_d (x^2 - t x + |z|^2) does) confirmed by exact
+// division are split off before the search: prim becomes the quotient, the
+// element leaves the set, and weights and window are recomputed for the
+// quotient's leading coefficient.  Their factors go to P.peeled (and into the
+// result).  This removes the flood of candidates from many rational roots.
+rfr_status peel_singletons(Prepared &P, std::string &err);
 
 // Search plan of the n-1 searched elements.
 inline void split_halves(int n, int &na, int &nb) {

@@ -99,6 +99,7 @@ static rfr_status serve_poly(rfr_ctx *ctx, RootBuf &rb, const int64_t *coeffs, i
     std::vector<Pat> cands;
     rfr_result *res = nullptr;
     rfr_status st = prepare_dev(rb, coeffs, degree, P, err);
+    if (st == RFR_OK) st = peel_singletons(P, err);
     if (st != RFR_OK) st = fail(st, err);
     double t1 = now_ms(), t2 = t1;
     if (st == RFR_OK && P.n <= 1) {

@@ -297,3 +297,55 @@ def test_multi_chunk_gather_batched_matches_golden(R, tmp_path):
             assert r == (e["content"], [tuple(f) for f in e["factors"]]), w.seed
     finally:
         _restore_tuning(R, tmp_path, lgs)
+
+
+def _sympy_factor(coeffs):
+    """(content, canonical factors) of the complete factorisation (sympy.factor_list)."""
+    import sympy
+    X = sympy.Symbol("x")
+    c, fl = sympy.factor_list(sympy.Poly(list(reversed([int(v) for v in coeffs])), X))
+    c = int(c)
+    facs = []
+    for f, m in fl:
+        cs = [int(v) for v in reversed(f.all_coeffs())]
+        if cs[-1] < 0:
+            cs = [-v for v in cs]
+            c = -c if m % 2 else c
+        facs.extend([cs] * m)
+    return c, O.canonical(facs)
+
+
+def test_single_element_factors_split_off(ctx):
+    # many rational roots (or integer quadratic pair factors) make every
+    # subset of them a factor: 2^k candidates.  Such factors are confirmed one
+    # element at a time and split off before the search; the result is the
+    # complete factorisation (sympy's factor_list as the definition).
+    cases = []
+    p = [1]
+    for k in range(1, 15):
+        p = O.poly_mul_exact(p, [-k, 1])          # (x-1)...(x-14): 2^13 candidate patterns
+    cases.append(p)
+    q = W.rand_poly(W._rng(7003), 12, -50, 50)
+    for k in (1, 2, 4, 5, 7, 8, 10, 11, 13, 14):
+        q = O.poly_mul_exact(q, [k, 3])           # (3x + k), non-monic rational roots
+    cases.append(q)
+    r = [1]
+    for k in range(1, 9):
+        r = O.poly_mul_exact(r, [k * k, 0, 1])    # x^2 + k^2: integer pair factors
+    cases.append(r)
+    s = [1, 0, -2]                                # both kinds beside x^2 - 2 and a random factor
+    for k in range(1, 7):
+        s = O.poly_mul_exact(s, [-k, 1])
+    for k in range(1, 4):
+        s = O.poly_mul_exact(s, [k * k, 0, 1])
+    s = O.poly_mul_exact(s, W.rand_poly(W._rng(7004), 10, -9, 9))
+    cases.append(s)
+    for c in cases:
+        say("single-element factors, degree", len(c) - 1)
+        got = ctx.factor(c)
+        assert got == _sympy_factor(c)
+        cont, facs = got
+        prod = [cont]
+        for f in facs:
+            prod = O.poly_mul_exact(prod, list(f))
+        assert prod == c
