@@ -824,40 +824,51 @@ __device__ __forceinline__ void join_semi(const JobArgs &J, uint32_t s, int b, i
     const uint64_t s_hi = LB == 0 ? ~0ull : (s_lo + ((1ull << (64 - LB)) - 1));
     const uint64_t t_lo = J.t_lo, t_hi = J.t_hi;
     const uint64_t cellw = 1ull << shc;
-    const bool fast = t_lo <= cellw && t_hi <= cellw;
+    const bool fast = t_lo <= cellw && t_hi <= cellw && LB <= 32;
+    // 32-bit views of the keys: loc = key bits [63 - LB, 32 - LB] (the bits
+    // below the sub-bucket's), so the cell is loc >> csh and loc & omask is the
+    // key's offset in its cell without its low sh bits.  Near-edge flags taken
+    // from that truncated offset are a superset of the exact ones: they only
+    // send a few more keys to the neighbour-cell test, and every pair is
+    // compared exactly in the end.
+    const int sh = 32 - LB, csh = 32 - CB3;
+    const uint32_t omask = (1u << csh) - 1;
+    auto loc = [sh](uint64_t key) { return (uint32_t)(key >> sh); };
     bool lists = false;
     if (fast) {
+        const uint64_t om = cellw - 1;
+        const uint32_t lo_thr = (uint32_t)min(t_hi >> sh, (uint64_t)omask);        // near the low edge: off <= lo_thr
+        const uint32_t hi_thr = t_lo > om ? 0u : (uint32_t)((om - t_lo) >> sh);  // near the high edge: off >= hi_thr
         // B' marks its cells
 #pragma unroll
         for (int k = 0; k < KP3; ++k)
-            if (tid + k * NT3 < nb) mark1(bm, dig(kk[1][k], shc, NC - 1));
+            if (tid + k * NT3 < nb) mark1(bm, loc(kk[1][k]) >> csh);
         __syncthreads();
         // A keys whose window meets a marked cell.  Every slot's own-cell word
         // is read first with no branch (the reads overlap; an unused slot reads
-        // a stale but in-range cell), the bit tests follow; the rare keys within
-        // a window of their cell's edge take a second pass for the neighbour.
+        // a stale but in-range cell), the bit tests follow; the rare keys near
+        // their cell's edge take a second pass for the neighbour.
         uint32_t hits = 0, elo = 0, ehi = 0;
         {
             uint32_t cl[KP3], wd[KP3];
 #pragma unroll
-            for (int k = 0; k < KP3; ++k) cl[k] = dig(kk[0][k], shc, NC - 1);
+            for (int k = 0; k < KP3; ++k) cl[k] = loc(kk[0][k]) >> csh;
 #pragma unroll
             for (int k = 0; k < KP3; ++k) wd[k] = bm[cl[k] >> 5];
-            const uint64_t om = (1ull << shc) - 1;
 #pragma unroll
             for (int k = 0; k < KP3; ++k) {
                 const bool live = tid + k * NT3 < na;
-                const uint64_t off = kk[0][k] & om;
+                const uint32_t off = loc(kk[0][k]) & omask;
                 hits |= (uint32_t)(live && ((wd[k] >> (cl[k] & 31)) & 1u)) << k;
-                elo |= (uint32_t)(live && off < t_hi) << k;
-                ehi |= (uint32_t)(live && om - off < t_lo) << k;
+                elo |= (uint32_t)(live && off <= lo_thr) << k;
+                ehi |= (uint32_t)(live && off >= hi_thr) << k;
             }
         }
         if ((elo | ehi) & ~hits) {
 #pragma unroll
             for (int k = 0; k < KP3; ++k) {  // static slot indices keep kk in registers
                 if (!(((elo | ehi) & ~hits) >> k & 1u)) continue;
-                if (window_hits<NC>(bm, dig(kk[0][k], shc, NC - 1), (elo >> k) & 1u, (ehi >> k) & 1u))
+                if (window_hits<NC>(bm, loc(kk[0][k]) >> csh, (elo >> k) & 1u, (ehi >> k) & 1u))
                     hits |= 1u << k;
             }
         }
@@ -868,7 +879,7 @@ __device__ __forceinline__ void join_semi(const JobArgs &J, uint32_t s, int b, i
             if ((hits >> k) & 1u) {
                 if (o < LCAP3) LA[o] = kk[0][k];
                 ++o;
-                mark_window<NC>(bmA, dig(kk[0][k], shc, NC - 1), (elo >> k) & 1u, (ehi >> k) & 1u);
+                mark_window<NC>(bmA, loc(kk[0][k]) >> csh, (elo >> k) & 1u, (ehi >> k) & 1u);
             }
         __syncthreads();
         const uint32_t nla = L.nl[0];
@@ -876,7 +887,7 @@ __device__ __forceinline__ void join_semi(const JobArgs &J, uint32_t s, int b, i
             // B' keys in those cells
             uint32_t bh = 0, cl[KP3], wd[KP3];
 #pragma unroll
-            for (int k = 0; k < KP3; ++k) cl[k] = dig(kk[1][k], shc, NC - 1);
+            for (int k = 0; k < KP3; ++k) cl[k] = loc(kk[1][k]) >> csh;
 #pragma unroll
             for (int k = 0; k < KP3; ++k) wd[k] = bmA[cl[k] >> 5];
 #pragma unroll
@@ -919,7 +930,7 @@ __device__ __forceinline__ void join_semi(const JobArgs &J, uint32_t s, int b, i
         if (tid + k * NT3 >= na) continue;
         const uint64_t a = kk[0][k];
         if (fast) {
-            const uint32_t c = dig(a, shc, NC - 1);
+            const uint32_t c = loc(a) >> csh;
             if (c != 0 && c != NC - 1) continue;
         }
         const bool low_edge = (a - s_lo) < t_hi;
