@@ -41,7 +41,7 @@ constexpr int NTS = 256;          // threads of the small-search kernel
 constexpr int MAXT = 256;         // tile rows staged per gather chunk
 // ---- K4/K5: candidate keys -> patterns
 constexpr int KCAP_MAX = 4096;    // key pairs held per search
-constexpr int RBITS_LOG = 16;     // LDS bitmap of candidate-key prefixes
+constexpr int RBITS_LOG = 18;     // LDS bitmap of candidate-key prefixes
 constexpr int RBITS = 1 << RBITS_LOG;
 constexpr int MAX_HALF = 34;      // elements per half (2^34 keys)
 constexpr int MAX_CHUNK_BITS = 8; // half A streamed in at most 2^8 chunks

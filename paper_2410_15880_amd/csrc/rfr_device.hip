@@ -1137,7 +1137,8 @@ __global__ __launch_bounds__(NT1) void k_recover_few(JobArgs Jarg, Multi M) {
 
 // Pattern recovery for many candidate keys: re-enumerate the half (same Gray
 // walk as K1, no stores) and look every key up in an LDS bitmap of candidate
-// key prefixes, confirming hits against the list.
+// key prefixes (2^RBITS_LOG bits), confirming a hit by a binary search in the
+// sorted candidate list.
 template <bool MULTI>
 __global__ __launch_bounds__(NT1) void k_recover(JobArgs Jarg, Multi M) {
     const JobArgs *Jp;
@@ -1159,13 +1160,33 @@ __global__ __launch_bounds__(NT1) void k_recover(JobArgs Jarg, Multi M) {
     if (tid < H.m) s_w[tid] = J.wts[blockIdx.y][tid];
     for (int i = tid; i < RBITS / 32; i += NT1) s_bits[i] = 0;
     __syncthreads();
-    for (uint32_t i = tid; i < cnt; i += NT1) {
-        const uint64_t k = J.kp[2 * i + half];
+    // the candidate keys, padded with ~0 to a power of two and sorted (bitonic)
+    // so that a key passing the prefix bitmap takes a binary search
+    uint32_t np = 1;
+    while (np < cnt) np <<= 1;
+    for (uint32_t i = tid; i < np; i += NT1) {
+        const uint64_t k = i < cnt ? J.kp[2 * i + half] : ~0ull;
         s_list[i] = k;
-        const uint32_t h = (uint32_t)(k >> (64 - RBITS_LOG));
-        atomicOr(&s_bits[h >> 5], 1u << (h & 31));
+        if (i < cnt) {
+            const uint32_t h = (uint32_t)(k >> (64 - RBITS_LOG));
+            atomicOr(&s_bits[h >> 5], 1u << (h & 31));
+        }
     }
     __syncthreads();
+    for (uint32_t k = 2; k <= np; k <<= 1)
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = tid; i < np; i += NT1) {
+                const uint32_t ixj = i ^ j;
+                if (ixj > i) {
+                    const uint64_t a = s_list[i], b = s_list[ixj];
+                    if ((a > b) == ((i & k) == 0)) {
+                        s_list[i] = b;
+                        s_list[ixj] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
 
     uint64_t slo = J.kbase[half];
     for (int i = 0; i < H.L; ++i)
@@ -1181,15 +1202,22 @@ __global__ __launch_bounds__(NT1) void k_recover(JobArgs Jarg, Multi M) {
         if (act) {
             const uint32_t hb = (uint32_t)(key >> (64 - RBITS_LOG));
             if ((s_bits[hb >> 5] >> (hb & 31)) & 1) {
-                for (uint32_t i = 0; i < cnt; ++i) {
-                    if (s_list[i] == key) {
-                        const uint64_t pat = ((uint64_t)tid | (g << H.L)) | J.pbase[half];
-                        const uint32_t r = atomicAdd(&J.rec_count[half], 1u);
-                        if (r < J.kcap) {
-                            J.rec[((size_t)half * J.kcap + r) * 2] = key;
-                            J.rec[((size_t)half * J.kcap + r) * 2 + 1] = pat;
-                        }
-                        break;
+                uint32_t lo = 0, len = (uint32_t)cnt;  // first of s_list[0, cnt) not below key
+                while (len > 0) {
+                    const uint32_t half_len = len >> 1;
+                    if (s_list[lo + half_len] < key) {
+                        lo += half_len + 1;
+                        len -= half_len + 1;
+                    } else {
+                        len = half_len;
+                    }
+                }
+                if (lo < cnt && s_list[lo] == key) {
+                    const uint64_t pat = ((uint64_t)tid | (g << H.L)) | J.pbase[half];
+                    const uint32_t r = atomicAdd(&J.rec_count[half], 1u);
+                    if (r < J.kcap) {
+                        J.rec[((size_t)half * J.kcap + r) * 2] = key;
+                        J.rec[((size_t)half * J.kcap + r) * 2 + 1] = pat;
                     }
                 }
             }

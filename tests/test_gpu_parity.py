@@ -349,3 +349,26 @@ def test_single_element_factors_split_off(ctx):
         for f in facs:
             prod = O.poly_mul_exact(prod, list(f))
         assert prod == c
+
+
+def test_maximum_size_search_recovers_planted_factors(R):
+    # the largest served size: a degree-124 product of random degree-40 and
+    # degree-84 factors (coefficients in [-1000, 1000]) has n = 65 elements,
+    # so both halves hold 2^32 keys (about 80 GB of tables): level-1 buckets
+    # of more than one gather chunk, the many-candidate recovery, and every
+    # index past 32 bits.  The result must be the two drawn factors (random
+    # dense factors of this size are irreducible) and multiply back to p.
+    rng = W._rng(9101)
+    f = W.rand_poly(rng, 40, -1000, 1000)
+    g = W.rand_poly(rng, 84, -1000, 1000)
+    p = O.poly_mul_exact(f, g)
+    with R.Context(0) as c:
+        say("maximum size: degree %d" % (len(p) - 1))
+        r = c.factor_full(p)
+        say("  n=%d candidates=%d search %.0f ms" % (r["n"], r["n_candidates"], r["ms_search"]))
+    assert r["n"] == 65
+    assert r["factors"] == O.canonical([O.primitive(f), O.primitive(g)])
+    prod = [r["content"]]
+    for q in r["factors"]:
+        prod = O.poly_mul_exact(prod, list(q))
+    assert prod == p
