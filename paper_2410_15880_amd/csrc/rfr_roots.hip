@@ -311,14 +311,17 @@ __global__ __launch_bounds__(ROOT_THREADS) void k_roots(const RootJob *jobs, int
     C2 c{mk(z.re), mk(z.im)};
     C2 step;
     double radius;
-    // Newton converges quadratically from the FP64 root: once a step is below
-    // 1e-20 of the root the next would be below double-double resolution
-    for (int k = 0; k < ROOT_POLISH; ++k) {
+    // Newton converges quadratically from the FP64 root.  Once a step is below
+    // 1e-20 of the root, the point it was computed at is kept: its disc
+    // (radius from that same evaluation) is already far below what the
+    // weights need, so no further evaluation is spent on the last few digits.
+    bool conv = false;
+    for (int k = 0; k < ROOT_POLISH && !conv; ++k) {
         newton_c(s_add, s_aa, d, c, step, radius);
-        c = csub(c, step);
-        if (cabs_d(step) <= 1e-20 * fmax(cabs_d(c), 1e-300)) break;
+        conv = cabs_d(step) <= 1e-20 * fmax(cabs_d(c), 1e-300);
+        if (!conv) c = csub(c, step);
     }
-    newton_c(s_add, s_aa, d, c, step, radius);
+    if (!conv) newton_c(s_add, s_aa, d, c, step, radius);
     RootOut out;
     out.re_hi = c.re.hi;
     out.re_lo = c.re.lo;
@@ -331,12 +334,13 @@ __global__ __launch_bounds__(ROOT_THREADS) void k_roots(const RootJob *jobs, int
     if (fabs(to_d(c.im)) <= radius) {
         D2 x = c.re, sx;
         double rx;
-        for (int k = 0; k < ROOT_POLISH; ++k) {
+        bool convr = false;
+        for (int k = 0; k < ROOT_POLISH && !convr; ++k) {
             newton_r(s_add, s_aa, d, x, sx, rx);
-            x = sub(x, sx);
-            if (fabs(to_d(sx)) <= 1e-20 * fmax(fabs(to_d(x)), 1e-300)) break;
+            convr = fabs(to_d(sx)) <= 1e-20 * fmax(fabs(to_d(x)), 1e-300);
+            if (!convr) x = sub(x, sx);
         }
-        newton_r(s_add, s_aa, d, x, sx, rx);
+        if (!convr) newton_r(s_add, s_aa, d, x, sx, rx);
         out.x_hi = x.hi;
         out.x_lo = x.lo;
         out.rx = rx;
