@@ -25,7 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# algorithmic HBM bytes per table key for each stage (see DESIGN.md):
+# algorithmic HBM bytes per table key for each stage:
 # K1 writes each key once; K2 reads and writes it; K3 reads it; K0/K4 only
 # enumerate (no table traffic); the scans touch per-workgroup counters only.
 STAGE_BYTES_PER_KEY = {"count": 0, "scan": 0, "enum_partition": 8, "tile_sort": 16, "sort_join": 8,
@@ -213,8 +213,8 @@ def main():
         print(json.dumps({"copy_probe_bytes": src.numel() * 8}))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(independent polynomials would shard with no communication; see DESIGN.md).",
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(independent polynomials would shard with no communication).",
               file=sys.stderr)
         sys.exit(2)
 
