@@ -1489,6 +1489,8 @@ int chunk_bits(int n, size_t ws_bytes) {
     return -1;
 }
 
+__global__ __launch_bounds__(NTS) void k_small_one(SmallJob S);  // below, with the batch's small searches
+
 rfr_status enqueue_recombine(const uint64_t *w, int n, uint64_t t_lo, uint64_t t_hi, void *ws,
                              size_t ws_bytes, hipStream_t st, uint64_t *cand, uint64_t cap,
                              uint64_t *count, StageEvents *ev, std::string &err) {
@@ -1506,6 +1508,29 @@ rfr_status enqueue_recombine(const uint64_t *w, int n, uint64_t t_lo, uint64_t t
     }
     int na, nb;
     split_halves(n, na, nb);
+    if (na <= SMALL_HALF && nb <= SMALL_HALF) {
+        // both halves fit one workgroup's LDS: the whole search is one launch
+        SmallJob S{};
+        S.na = na;
+        S.nb = nb;
+        for (int t = 0; t < n - 1; ++t) S.w[t] = w[t];
+        S.t_lo = t_lo;
+        S.t_hi = t_hi;
+        S.out = cand;
+        S.out_count = count;
+        S.cap = cap;
+        auto rec = [&](int i) {
+            if (ev && ev->ev[i]) (void)hipEventRecord((hipEvent_t)ev->ev[i], st);
+        };
+        rec(0);
+        hipLaunchKernelGGL(k_small_one, dim3(1), dim3(NTS), 0, st, S);
+        for (int i = 1; i < 7; ++i) rec(i);
+        if (hipGetLastError() != hipSuccess) {
+            err = "kernel launch failed";
+            return RFR_EDEVICE;
+        }
+        return RFR_OK;
+    }
     const int c = chunk_bits(n, ws_bytes);
     if (c < 0) {
         err = "rfr_recombine_dev: workspace too small";
@@ -1647,101 +1672,124 @@ hipError_t MultiLaunch::launch(const JobArgs *jobs_dev, const uint32_t *bases_de
 // bits together with its pattern index, then every a probes the bins its
 // cyclic window overlaps and emits pattern pairs directly.  Workgroups are
 // persistent and take the next job (largest first) from an atomic counter.
-__global__ __launch_bounds__(NTS) void k_small(const SmallJob *jobs, int njobs, uint32_t *queue) {
-    __shared__ uint64_t s_a[1 << SMALL_HALF];
-    __shared__ uint64_t s_b[1 << SMALL_HALF];
-    __shared__ uint16_t s_bi[1 << SMALL_HALF];
-    __shared__ uint32_t s_bin[NB3 + 1];
-    __shared__ uint64_t s_tmp[NTS / 64 + 2];
-    __shared__ int s_job;
-    __shared__ unsigned long long s_cnt;
+// LDS of one small search.
+struct SmallLds {
+    uint64_t a[1 << SMALL_HALF];
+    uint64_t b[1 << SMALL_HALF];
+    uint16_t bi[1 << SMALL_HALF];
+    uint32_t bin[NB3 + 1];
+    uint64_t tmp[NTS / 64 + 2];
+    unsigned long long cnt;
+};
+
+// One whole search in a workgroup's LDS: half A's sums in pattern order, half
+// B' counting-sorted by its top LB3 bits, and every a's window looked up among
+// the bins it covers.
+__device__ void small_search(const SmallJob &S, SmallLds &L) {
+    uint64_t *s_a = L.a, *s_b = L.b, *s_tmp = L.tmp;
+    uint16_t *s_bi = L.bi;
+    uint32_t *s_bin = L.bin;
+    unsigned long long &s_cnt = L.cnt;
     const int tid = threadIdx.x;
     constexpr int KPS = (1 << SMALL_HALF) / NTS;
+    const int na = S.na, nb = S.nb;
+    const uint32_t NA = 1u << na, NBk = 1u << nb;
+    for (int i = tid; i < NB3; i += NTS) s_bin[i] = 0;
+    if (tid == 0) s_cnt = 0;
+    for (uint32_t i = tid; i < NA; i += NTS) {
+        uint64_t v = 0;
+        for (int e = 0; e < na; ++e)
+            if ((i >> e) & 1) v += S.w[e];
+        s_a[i] = v;
+    }
+    __syncthreads();
+    uint64_t kb[KPS];
+    uint32_t rk[KPS];
+#pragma unroll
+    for (int k = 0; k < KPS; ++k) {
+        const uint32_t i = tid + k * NTS;
+        if (i < NBk) {
+            uint64_t v = 0;
+            for (int e = 0; e < nb; ++e)
+                if ((i >> e) & 1) v -= S.w[na + e];
+            kb[k] = v;
+            rk[k] = atomicAdd(&s_bin[(uint32_t)(v >> (64 - LB3))], 1u);
+        }
+    }
+    __syncthreads();
+    lds_excl_scan<NTS, NB3 / NTS>(s_bin, NB3, s_tmp);
+    if (tid == 0) s_bin[NB3] = NBk;
+#pragma unroll
+    for (int k = 0; k < KPS; ++k) {
+        const uint32_t i = tid + k * NTS;
+        if (i < NBk) {
+            const uint32_t p = s_bin[(uint32_t)(kb[k] >> (64 - LB3))] + rk[k];
+            s_b[p] = kb[k];
+            s_bi[p] = (uint16_t)i;
+        }
+    }
+    __syncthreads();
+    const uint64_t t_lo = S.t_lo, t_hi = S.t_hi;
+    for (uint32_t i = tid; i < NA; i += NTS) {
+        const uint64_t a = s_a[i];
+        // the cyclic window [a - t_hi, a + t_lo] as up to two plain ranges
+        uint64_t lo[2], hi[2];
+        int nr = 0;
+        if (a >= t_hi) {
+            lo[0] = a - t_hi;
+        } else {
+            lo[0] = 0;
+            lo[1] = a - t_hi;  // wraps: [2^64 - (t_hi - a), 2^64)
+            hi[1] = ~0ull;
+            nr = 1;
+        }
+        if (a <= ~0ull - t_lo) {
+            hi[0] = a + t_lo;
+        } else {
+            hi[0] = ~0ull;
+            lo[1] = 0;
+            hi[1] = a + t_lo;  // wraps: [0, a + t_lo - 2^64]
+            nr = 1;
+        }
+        for (int r = 0; r <= nr; ++r) {
+            const uint32_t b0 = (uint32_t)(lo[r] >> (64 - LB3)), b1 = (uint32_t)(hi[r] >> (64 - LB3));
+            const uint32_t e = s_bin[b1 + 1];
+            for (uint32_t q = s_bin[b0]; q < e; ++q) {
+                const uint64_t bk = s_b[q];
+                if (bk < lo[r] || bk > hi[r]) continue;
+                const uint32_t pb = s_bi[q];
+                if (i == 0 && pb == 0) continue;  // the empty pattern
+                const unsigned long long o = atomicAdd(&s_cnt, 1ull);
+                if (o < S.cap) {
+                    S.out[2 * o] = i;
+                    S.out[2 * o + 1] = pb;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) *S.out_count = s_cnt > S.cap ? ~0ull : s_cnt;
+    __syncthreads();
+}
+
+// Small searches of a batch: a persistent grid takes them from an atomic queue.
+__global__ __launch_bounds__(NTS) void k_small(const SmallJob *jobs, int njobs, uint32_t *queue) {
+    __shared__ SmallLds L;
+    __shared__ int s_job;
+    const int tid = threadIdx.x;
     for (;;) {
         if (tid == 0) s_job = (int)atomicAdd(queue, 1u);
         __syncthreads();
         const int j = s_job;
         if (j >= njobs) return;
-        const SmallJob &S = jobs[j];
-        const int na = S.na, nb = S.nb;
-        const uint32_t NA = 1u << na, NBk = 1u << nb;
-        for (int i = tid; i < NB3; i += NTS) s_bin[i] = 0;
-        if (tid == 0) s_cnt = 0;
-        for (uint32_t i = tid; i < NA; i += NTS) {
-            uint64_t v = 0;
-            for (int e = 0; e < na; ++e)
-                if ((i >> e) & 1) v += S.w[e];
-            s_a[i] = v;
-        }
-        __syncthreads();
-        uint64_t kb[KPS];
-        uint32_t rk[KPS];
-#pragma unroll
-        for (int k = 0; k < KPS; ++k) {
-            const uint32_t i = tid + k * NTS;
-            if (i < NBk) {
-                uint64_t v = 0;
-                for (int e = 0; e < nb; ++e)
-                    if ((i >> e) & 1) v -= S.w[na + e];
-                kb[k] = v;
-                rk[k] = atomicAdd(&s_bin[(uint32_t)(v >> (64 - LB3))], 1u);
-            }
-        }
-        __syncthreads();
-        lds_excl_scan<NTS, NB3 / NTS>(s_bin, NB3, s_tmp);
-        if (tid == 0) s_bin[NB3] = NBk;
-#pragma unroll
-        for (int k = 0; k < KPS; ++k) {
-            const uint32_t i = tid + k * NTS;
-            if (i < NBk) {
-                const uint32_t p = s_bin[(uint32_t)(kb[k] >> (64 - LB3))] + rk[k];
-                s_b[p] = kb[k];
-                s_bi[p] = (uint16_t)i;
-            }
-        }
-        __syncthreads();
-        const uint64_t t_lo = S.t_lo, t_hi = S.t_hi;
-        for (uint32_t i = tid; i < NA; i += NTS) {
-            const uint64_t a = s_a[i];
-            // the cyclic window [a - t_hi, a + t_lo] as up to two plain ranges
-            uint64_t lo[2], hi[2];
-            int nr = 0;
-            if (a >= t_hi) {
-                lo[0] = a - t_hi;
-            } else {
-                lo[0] = 0;
-                lo[1] = a - t_hi;  // wraps: [2^64 - (t_hi - a), 2^64)
-                hi[1] = ~0ull;
-                nr = 1;
-            }
-            if (a <= ~0ull - t_lo) {
-                hi[0] = a + t_lo;
-            } else {
-                hi[0] = ~0ull;
-                lo[1] = 0;
-                hi[1] = a + t_lo;  // wraps: [0, a + t_lo - 2^64]
-                nr = 1;
-            }
-            for (int r = 0; r <= nr; ++r) {
-                const uint32_t b0 = (uint32_t)(lo[r] >> (64 - LB3)), b1 = (uint32_t)(hi[r] >> (64 - LB3));
-                const uint32_t e = s_bin[b1 + 1];
-                for (uint32_t q = s_bin[b0]; q < e; ++q) {
-                    const uint64_t bk = s_b[q];
-                    if (bk < lo[r] || bk > hi[r]) continue;
-                    const uint32_t pb = s_bi[q];
-                    if (i == 0 && pb == 0) continue;  // the empty pattern
-                    const unsigned long long o = atomicAdd(&s_cnt, 1ull);
-                    if (o < S.cap) {
-                        S.out[2 * o] = i;
-                        S.out[2 * o + 1] = pb;
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        if (tid == 0) *S.out_count = s_cnt > S.cap ? ~0ull : s_cnt;
-        __syncthreads();
+        small_search(jobs[j], L);
     }
+}
+
+// One small search passed by value (a plain or served request).
+__global__ __launch_bounds__(NTS) void k_small_one(SmallJob S) {
+    __shared__ SmallLds L;
+    small_search(S, L);
 }
 
 __global__ void k_small_init(uint32_t *queue) {
