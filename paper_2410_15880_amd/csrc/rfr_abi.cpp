@@ -110,7 +110,7 @@ rfr_status prepare_dev(RootBuf &b, const int64_t *coeffs, int degree, Prepared &
         std::memcpy(b.host, P.prim.data(), (size_t)(d + 1) * 8);
         *(RootJob *)(b.host + ROOT_O_JOB) = RootJob{(const int64_t *)b.dev, d, (RootOut *)(b.dev + ROOT_O_OUT)};
         bool ok = hipMemcpyAsync(b.dev, b.host, ROOT_O_OUT, hipMemcpyHostToDevice, b.stream) == hipSuccess;
-        ok = ok && launch_roots((const RootJob *)(b.dev + ROOT_O_JOB), 1, b.stream) == hipSuccess;
+        ok = ok && launch_roots((const RootJob *)(b.dev + ROOT_O_JOB), 1, d, ROOT_LANES, b.stream) == hipSuccess;
         ok = ok && hipMemcpyAsync(b.host + ROOT_O_OUT, b.dev + ROOT_O_OUT, (size_t)d * sizeof(RootOut),
                                   hipMemcpyDeviceToHost, b.stream) == hipSuccess;
         ok = ok && hipStreamSynchronize(b.stream) == hipSuccess;

@@ -145,8 +145,10 @@ static rfr_status device_roots(BatchState *B, hipStream_t st, std::vector<Prepar
         hj[k] = RootJob{(const int64_t *)(B->rdev) + co[i], (int)P[i].prim.size() - 1,
                         (RootOut *)(B->rdev + o_out) + ro[i]};
     }
+    int dmax = 2;
+    for (int i : jobs) dmax = std::max(dmax, (int)P[i].prim.size() - 1);
     bool ok = hipMemcpyAsync(B->rdev, B->rhost, o_out, hipMemcpyHostToDevice, st) == hipSuccess;
-    ok = ok && launch_roots((const RootJob *)(B->rdev + o_jobs), (int)jobs.size(), st) == hipSuccess;
+    ok = ok && launch_roots((const RootJob *)(B->rdev + o_jobs), (int)jobs.size(), dmax, 1, st) == hipSuccess;
     ok = ok && hipMemcpyAsync(B->rhost + o_out, B->rdev + o_out, nro * sizeof(RootOut), hipMemcpyDeviceToHost,
                               st) == hipSuccess;
     ok = ok && hipStreamSynchronize(st) == hipSuccess;

@@ -9,7 +9,8 @@
 
 namespace rfr {
 
-constexpr int ROOT_THREADS = 256;  // one thread per root (degree <= RFR_MAX_DEGREE = 256)
+constexpr int ROOT_LANES = 4;                                // lanes per root for a single polynomial
+constexpr int ROOT_THREADS = ROOT_LANES * RFR_MAX_DEGREE;  // workgroup size at most
 constexpr int ROOT_MAXIT = 400;    // Aberth iterations at most
 constexpr int ROOT_POLISH = 6;     // double-double Newton steps at most
 
@@ -21,6 +22,9 @@ struct RootJob {
     RootOut *out;
 };
 
-hipError_t launch_roots(const RootJob *jobs_dev, int njobs, hipStream_t st);
+// One workgroup per job with `lanes` (1 or ROOT_LANES) threads per root of
+// the largest degree: a batch takes one lane per root (more polynomials in
+// flight), a single polynomial ROOT_LANES (shorter dependent chains).
+hipError_t launch_roots(const RootJob *jobs_dev, int njobs, int max_degree, int lanes, hipStream_t st);
 
 }  // namespace rfr

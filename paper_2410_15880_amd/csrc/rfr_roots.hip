@@ -1,5 +1,6 @@
 // Device root finding for batches of polynomials (the roots -> elements step
-// ahead of the search): one workgroup per polynomial, one thread per root.
+// ahead of the search): one workgroup per polynomial, one thread per root in a
+// batch, a group of ROOT_LANES threads per root for a single polynomial.
 //
 //   1. starting points on circles from the Newton polygon of (i, log|a_i|);
 //   2. simultaneous Aberth-Ehrlich iteration in FP64 (every root updated from
@@ -112,98 +113,153 @@ __device__ inline double cabs_d(C2 a) { return hypot(to_d(a.re), to_d(a.im)); }
 constexpr double kHornerU = 16.0 * 5.0e-32;  // > 16 * 2^-104 (complex double-double mul-add)
 constexpr double kHornerUR = 8.0 * 5.0e-32;  // real double-double mul-add
 
-// Newton step p(z)/p'(z) and inclusion radius at z (complex double-double).
-__device__ void newton_c(const D2 *a, const double *aa, int d, C2 z, C2 &step, double &radius) {
+// ---------------------------------------------------------------- lane groups
+// A root may be served by L lanes (L = 1 or ROOT_LANES, consecutive lanes of a
+// wavefront): lane l evaluates the l-th run of m = ceil((d+1)/L) coefficients
+// by Horner, and the runs are combined with the powers x^(l m).  The group
+// sums are butterflies; each step adds the same two operands in either order,
+// which FP64 and double-double addition do bit for bit alike, so every lane of
+// a group ends with identical values and takes identical steps.
+__device__ inline double gsum(double v, int L) {
+    for (int o = 1; o < L; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ inline D2 gsum(D2 v, int L) {
+    for (int o = 1; o < L; o <<= 1) v = add(v, D2{__shfl_xor(v.hi, o, 64), __shfl_xor(v.lo, o, 64)});
+    return v;
+}
+__device__ inline C2 gsum(C2 v, int L) { return {gsum(v.re, L), gsum(v.im, L)}; }
+
+// newton_ratio over a lane group.
+__device__ Z newton_ratio_group(const double *a, int d, Z z, int lane, int L) {
+    const int m = (d + L) / L;
+    const bool inside = zabs(z) <= 1.0;
+    const Z x = inside ? z : zdiv(Z{1, 0}, z);  // |z| > 1: y^d p(1/y) in y = 1/z
+    const int j0 = lane * m, j1 = min(j0 + m, d + 1);
+    Z P{0, 0}, dP{0, 0};
+    for (int j = j1 - 1; j >= j0; --j) {
+        dP = zadd(zmul(dP, x), P);
+        P = zadd(zmul(P, x), Z{a[inside ? j : d - j], 0});
+    }
+    Z pw{1, 0}, b = x;  // x^j0
+    for (int e = j0; e; e >>= 1) {
+        if (e & 1) pw = zmul(pw, b);
+        b = zmul(b, b);
+    }
+    const Z v = zmul(pw, P), dv = zmul(pw, dP);
+    const double sc = (double)j0;  // d/dx x^j0 P = x^j0 P' + j0 x^(j0 - 1) P
+    const Z val{gsum(v.re, L), gsum(v.im, L)};
+    Z der{gsum(dv.re, L), gsum(dv.im, L)};
+    if (L > 1) der = zadd(der, zdiv(Z{gsum(v.re * sc, L), gsum(v.im * sc, L)}, x));
+    if (inside) return zdiv(val, der);
+    return zdiv(zmul(z, val), zsub(zscale(val, (double)d), zmul(x, der)));
+}
+
+// newton_c over a lane group.  The evaluation error is bounded as for one
+// Horner run of length d (each lane's run is shorter) plus a margin of 64
+// units for the powers of x and the combination, which is far above their
+// few roundings.
+__device__ void newton_c_group(const D2 *a, const double *aa, int d, C2 z, int lane, int L, C2 &step,
+                               double &radius) {
     const double az = cabs_d(z);
-    if (az <= 1.0) {
-        C2 p{a[d], mk(0)}, dp{mk(0), mk(0)};
-        double s = aa[d], ds = 0;
-        for (int i = d - 1; i >= 0; --i) {
-            dp = cadd(cmul(dp, z), p);
-            p = cadd(cmul(p, z), C2{a[i], mk(0)});
-            ds = ds * az + s;
-            s = s * az + aa[i];
+    const bool inside = az <= 1.0;
+    const C2 x = inside ? z : cdiv(C2{mk(1), mk(0)}, z);
+    const double ax = inside ? az : cabs_d(x);
+    const int m = (d + L) / L;
+    const int j0 = lane * m, j1 = min(j0 + m, d + 1);
+    C2 P{mk(0), mk(0)}, dP{mk(0), mk(0)};
+    double sp = 0, sd = 0;
+    for (int j = j1 - 1; j >= j0; --j) {
+        const int i = inside ? j : d - j;
+        dP = cadd(cmul(dP, x), P);
+        P = cadd(cmul(P, x), C2{a[i], mk(0)});
+        sd = sd * ax + sp;
+        sp = sp * ax + aa[i];
+    }
+    C2 pw{mk(1), mk(0)}, b = x;  // x^j0 and |x|^j0
+    double apw = 1, ab = ax;
+    for (int e = j0; e; e >>= 1) {
+        if (e & 1) {
+            pw = cmul(pw, b);
+            apw *= ab;
         }
-        const double ep = 2.0 * d * kHornerU * s, edp = 2.0 * d * kHornerU * ds;
-        const double adp = cabs_d(dp) - edp;
-        step = cabs_d(dp) > 0 ? cdiv(p, dp) : C2{mk(0), mk(0)};
-        radius = adp > 0 ? d * (cabs_d(p) + ep) / adp * (1 + 1e-12) : INFINITY;
+        b = cmul(b, b);
+        ab *= ab;
+    }
+    const C2 val = gsum(cmul(pw, P), L);
+    C2 der = gsum(cmul(pw, dP), L);
+    const double S = gsum(apw * sp, L);
+    const double DS = gsum(apw * sd + (j0 > 0 ? (double)j0 * (apw / ax) * sp : 0.0), L);
+    if (L > 1) {
+        const C2 v = cmul(pw, P);
+        der = cadd(der, cdiv(gsum(C2{muld(v.re, (double)j0), muld(v.im, (double)j0)}, L), x));
+    }
+    const double kk = (2.0 * d + (L > 1 ? 64.0 : 0.0)) * kHornerU;
+    if (inside) {
+        const double ep = kk * S, edp = kk * DS;
+        const double adp = cabs_d(der) - edp;
+        step = cabs_d(der) > 0 ? cdiv(val, der) : C2{mk(0), mk(0)};
+        radius = adp > 0 ? d * (cabs_d(val) + ep) / adp * (1 + 1e-12) : INFINITY;
         return;
     }
-    const C2 y = cdiv(C2{mk(1), mk(0)}, z);
-    const double ay = cabs_d(y);
-    C2 q{a[0], mk(0)}, dq{mk(0), mk(0)};
-    double s = aa[0], ds = 0;
-    for (int i = 1; i <= d; ++i) {
-        dq = cadd(cmul(dq, y), q);
-        q = cadd(cmul(q, y), C2{a[i], mk(0)});
-        ds = ds * ay + s;
-        s = s * ay + aa[i];
-    }
-    const double eq = 2.0 * d * kHornerU * s, edq = 2.0 * d * kHornerU * ds;
-    const C2 den = csub(C2{muld(q.re, (double)d), muld(q.im, (double)d)}, cmul(y, dq));
-    const double aden = cabs_d(den) - d * eq - ay * edq;
-    step = cabs_d(den) > 0 ? cdiv(cmul(z, q), den) : C2{mk(0), mk(0)};
-    radius = aden > 0 ? d * az * (cabs_d(q) + eq) / aden * (1 + 1e-12) : INFINITY;
+    const double eq = kk * S, edq = kk * DS;
+    const C2 den = csub(C2{muld(val.re, (double)d), muld(val.im, (double)d)}, cmul(x, der));
+    const double aden = cabs_d(den) - d * eq - ax * edq;
+    step = cabs_d(den) > 0 ? cdiv(cmul(z, val), den) : C2{mk(0), mk(0)};
+    radius = aden > 0 ? d * az * (cabs_d(val) + eq) / aden * (1 + 1e-12) : INFINITY;
 }
 
-// The same on the real axis (real double-double).
-__device__ void newton_r(const D2 *a, const double *aa, int d, D2 x, D2 &step, double &radius) {
-    const double ax = fabs(to_d(x));
-    if (ax <= 1.0) {
-        D2 p = a[d], dp = mk(0);
-        double s = aa[d], ds = 0;
-        for (int i = d - 1; i >= 0; --i) {
-            dp = add(mul(dp, x), p);
-            p = add(mul(p, x), a[i]);
-            ds = ds * ax + s;
-            s = s * ax + aa[i];
+// newton_r over a lane group (real double-double), same bound.
+__device__ void newton_r_group(const D2 *a, const double *aa, int d, D2 xr, int lane, int L, D2 &step,
+                               double &radius) {
+    const double axr = fabs(to_d(xr));
+    const bool inside = axr <= 1.0;
+    const D2 x = inside ? xr : div(mk(1), xr);
+    const double ax = inside ? axr : fabs(to_d(x));
+    const int m = (d + L) / L;
+    const int j0 = lane * m, j1 = min(j0 + m, d + 1);
+    D2 P = mk(0), dP = mk(0);
+    double sp = 0, sd = 0;
+    for (int j = j1 - 1; j >= j0; --j) {
+        const int i = inside ? j : d - j;
+        dP = add(mul(dP, x), P);
+        P = add(mul(P, x), a[i]);
+        sd = sd * ax + sp;
+        sp = sp * ax + aa[i];
+    }
+    D2 pw = mk(1), b = x;
+    double apw = 1, ab = ax;
+    for (int e = j0; e; e >>= 1) {
+        if (e & 1) {
+            pw = mul(pw, b);
+            apw *= ab;
         }
-        const double ep = 2.0 * d * kHornerUR * s, edp = 2.0 * d * kHornerUR * ds;
-        const double adp = fabs(to_d(dp)) - edp;
-        step = to_d(dp) != 0 ? div(p, dp) : mk(0);
-        radius = adp > 0 ? d * (fabs(to_d(p)) + ep) / adp * (1 + 1e-12) : INFINITY;
+        b = mul(b, b);
+        ab *= ab;
+    }
+    const D2 val = gsum(mul(pw, P), L);
+    D2 der = gsum(mul(pw, dP), L);
+    const double S = gsum(apw * sp, L);
+    const double DS = gsum(apw * sd + (j0 > 0 ? (double)j0 * (apw / ax) * sp : 0.0), L);
+    if (L > 1) der = add(der, div(gsum(muld(mul(pw, P), (double)j0), L), x));
+    const double kk = (2.0 * d + (L > 1 ? 64.0 : 0.0)) * kHornerUR;
+    if (inside) {
+        const double ep = kk * S, edp = kk * DS;
+        const double adp = fabs(to_d(der)) - edp;
+        step = to_d(der) != 0 ? div(val, der) : mk(0);
+        radius = adp > 0 ? d * (fabs(to_d(val)) + ep) / adp * (1 + 1e-12) : INFINITY;
         return;
     }
-    const D2 y = div(mk(1), x);
-    const double ay = fabs(to_d(y));
-    D2 q = a[0], dq = mk(0);
-    double s = aa[0], ds = 0;
-    for (int i = 1; i <= d; ++i) {
-        dq = add(mul(dq, y), q);
-        q = add(mul(q, y), a[i]);
-        ds = ds * ay + s;
-        s = s * ay + aa[i];
-    }
-    const double eq = 2.0 * d * kHornerUR * s, edq = 2.0 * d * kHornerUR * ds;
-    const D2 den = sub(muld(q, (double)d), mul(y, dq));
-    const double aden = fabs(to_d(den)) - d * eq - ay * edq;
-    step = to_d(den) != 0 ? div(mul(x, q), den) : mk(0);
-    radius = aden > 0 ? d * ax * (fabs(to_d(q)) + eq) / aden * (1 + 1e-12) : INFINITY;
-}
-
-// p(z)/p'(z) in FP64; for |z| > 1 through the reversed polynomial.
-__device__ Z newton_ratio(const double *a, int d, Z z) {
-    if (zabs(z) <= 1.0) {
-        Z p{a[d], 0}, dp{0, 0};
-        for (int i = d - 1; i >= 0; --i) {
-            dp = zadd(zmul(dp, z), p);
-            p = zadd(zmul(p, z), Z{a[i], 0});
-        }
-        return zdiv(p, dp);
-    }
-    const Z y = zdiv(Z{1, 0}, z);
-    Z q{a[0], 0}, dq{0, 0};
-    for (int i = 1; i <= d; ++i) {
-        dq = zadd(zmul(dq, y), q);
-        q = zadd(zmul(q, y), Z{a[i], 0});
-    }
-    return zdiv(zmul(z, q), zsub(zscale(q, (double)d), zmul(y, dq)));
+    const double eq = kk * S, edq = kk * DS;
+    const D2 den = sub(muld(val, (double)d), mul(x, der));
+    const double aden = fabs(to_d(den)) - d * eq - ax * edq;
+    step = to_d(den) != 0 ? div(mul(xr, val), den) : mk(0);
+    radius = aden > 0 ? d * axr * (fabs(to_d(val)) + eq) / aden * (1 + 1e-12) : INFINITY;
 }
 
 __device__ inline bool finite(Z z) { return isfinite(z.re) && isfinite(z.im); }
 
-__global__ __launch_bounds__(ROOT_THREADS) void k_roots(const RootJob *jobs, int njobs) {
+__global__ __launch_bounds__(ROOT_THREADS) void k_roots(const RootJob *jobs, int njobs, int L) {
     const int j = blockIdx.x;
     if (j >= njobs) return;
     const RootJob J = jobs[j];
@@ -218,7 +274,7 @@ __global__ __launch_bounds__(ROOT_THREADS) void k_roots(const RootJob *jobs, int
     __shared__ int s_nh;
     if (d < 2 || d > RFR_MAX_DEGREE) return;  // the host handles linear inputs
 
-    for (int i = tid; i <= d; i += ROOT_THREADS) {
+    for (int i = tid; i <= d; i += (int)blockDim.x) {
         const int64_t c = J.coeffs[i];
         s_a[i] = (double)c;
         s_add[i] = from_i64(c);
@@ -257,41 +313,45 @@ __global__ __launch_bounds__(ROOT_THREADS) void k_roots(const RootJob *jobs, int
         s_z[tid] = Z{u * cs, u * sn};
     }
     __syncthreads();
-    // 2. simultaneous Aberth-Ehrlich iteration.  A root stops when its step is
-    //    below 1e-13 of its modulus, or small and no longer shrinking (the
-    //    FP64 evaluation noise floor); the double-double polish takes it from
-    //    there.  The workgroup iterates until every root has stopped.
-    Z z = tid < d ? s_z[tid] : Z{0, 0};
-    bool done = tid >= d;
+    // 2. simultaneous Aberth-Ehrlich iteration, L lanes per root (root
+    //    r = tid / L): the lanes share its Horner evaluation and the sum over
+    //    the other roots.  A root stops when its step is below 1e-13 of its
+    //    modulus, or small and no longer shrinking (the FP64 evaluation noise
+    //    floor); the double-double polish takes it from there.  The workgroup
+    //    iterates until every root has stopped.
+    const int r = tid / L, lane = tid % L;
+    Z z = r < d ? s_z[r] : Z{0, 0};
+    bool done = r >= d;
     double prev = INFINITY;
     for (int it = 0; it < ROOT_MAXIT; ++it) {
         Z wc{0, 0};
         bool upd = false;
         if (!done) {
-            const Z N = newton_ratio(s_a, d, z);
+            const Z N = newton_ratio_group(s_a, d, z, lane, L);
             // S = sum over the other roots of 1 / (z - z_q) = conj(w) / |w|^2,
-            // four independent partial sums so the divisions overlap; the own
-            // term is replaced by w = 1 and taken out at the end
-            double sr[4] = {0, 0, 0, 0}, si[4] = {0, 0, 0, 0};
-            int q = 0;
-            for (; q + 4 <= d; q += 4) {
+            // lane l taking q = l mod L, two partial sums so the divisions
+            // overlap; the own term is replaced by w = 1 and taken out at the end
+            double sr[2] = {0, 0}, si[2] = {0, 0};
+            int q = lane;
+            for (; q + L < d; q += 2 * L) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    Z w = zsub(z, s_z[q + u]);
-                    if (q + u == tid) w = Z{1, 0};
+                for (int u = 0; u < 2; ++u) {
+                    const int qq = q + u * L;
+                    Z w = zsub(z, s_z[qq]);
+                    if (qq == r) w = Z{1, 0};
                     const double inv = 1.0 / (w.re * w.re + w.im * w.im);
                     sr[u] += w.re * inv;
                     si[u] -= w.im * inv;
                 }
             }
-            for (; q < d; ++q) {
+            for (; q < d; q += L) {
                 Z w = zsub(z, s_z[q]);
-                if (q == tid) w = Z{1, 0};
+                if (q == r) w = Z{1, 0};
                 const double inv = 1.0 / (w.re * w.re + w.im * w.im);
                 sr[0] += w.re * inv;
                 si[0] -= w.im * inv;
             }
-            const Z S{(sr[0] + sr[1]) + (sr[2] + sr[3]) - 1.0, (si[0] + si[1]) + (si[2] + si[3])};
+            const Z S{gsum(sr[0] + sr[1], L) - 1.0, gsum(si[0] + si[1], L)};
             wc = zdiv(N, zsub(Z{1, 0}, zmul(N, S)));
             if (!finite(wc)) done = true;
             else upd = true;
@@ -299,29 +359,29 @@ __global__ __launch_bounds__(ROOT_THREADS) void k_roots(const RootJob *jobs, int
         __syncthreads();
         if (upd) {
             z = zsub(z, wc);
-            s_z[tid] = z;
+            if (lane == 0) s_z[r] = z;
             const double step = zabs(wc), scale = fmax(zabs(z), 1e-300);
             if (step <= 1e-13 * scale || (step <= 1e-9 * scale && step >= 0.5 * prev)) done = true;
             prev = step;
         }
         if (!__syncthreads_or(!done)) break;
     }
-    if (tid >= d) return;
-    // 3. complex double-double polish and inclusion radius
+    if (r >= d) return;
+    // 3. complex double-double polish and inclusion radius (the group's lanes
+    //    in step).  Newton converges quadratically from the FP64 root.  Once a
+    //    step is below 1e-20 of the root, the point it was computed at is kept:
+    //    its disc (radius from that same evaluation) is already far below what
+    //    the weights need, so no further evaluation is spent on the last digits.
     C2 c{mk(z.re), mk(z.im)};
     C2 step;
     double radius;
-    // Newton converges quadratically from the FP64 root.  Once a step is below
-    // 1e-20 of the root, the point it was computed at is kept: its disc
-    // (radius from that same evaluation) is already far below what the
-    // weights need, so no further evaluation is spent on the last few digits.
     bool conv = false;
     for (int k = 0; k < ROOT_POLISH && !conv; ++k) {
-        newton_c(s_add, s_aa, d, c, step, radius);
+        newton_c_group(s_add, s_aa, d, c, lane, L, step, radius);
         conv = cabs_d(step) <= 1e-20 * fmax(cabs_d(c), 1e-300);
         if (!conv) c = csub(c, step);
     }
-    if (!conv) newton_c(s_add, s_aa, d, c, step, radius);
+    if (!conv) newton_c_group(s_add, s_aa, d, c, lane, L, step, radius);
     RootOut out;
     out.re_hi = c.re.hi;
     out.re_lo = c.re.lo;
@@ -336,23 +396,26 @@ __global__ __launch_bounds__(ROOT_THREADS) void k_roots(const RootJob *jobs, int
         double rx;
         bool convr = false;
         for (int k = 0; k < ROOT_POLISH && !convr; ++k) {
-            newton_r(s_add, s_aa, d, x, sx, rx);
+            newton_r_group(s_add, s_aa, d, x, lane, L, sx, rx);
             convr = fabs(to_d(sx)) <= 1e-20 * fmax(fabs(to_d(x)), 1e-300);
             if (!convr) x = sub(x, sx);
         }
-        if (!convr) newton_r(s_add, s_aa, d, x, sx, rx);
+        if (!convr) newton_r_group(s_add, s_aa, d, x, lane, L, sx, rx);
         out.x_hi = x.hi;
         out.x_lo = x.lo;
         out.rx = rx;
     }
-    J.out[tid] = out;
+    if (lane == 0) J.out[r] = out;
 }
 
 }  // namespace droots
 
-hipError_t launch_roots(const RootJob *jobs_dev, int njobs, hipStream_t st) {
+hipError_t launch_roots(const RootJob *jobs_dev, int njobs, int max_degree, int lanes, hipStream_t st) {
     if (njobs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(droots::k_roots, dim3(njobs), dim3(ROOT_THREADS), 0, st, jobs_dev, njobs);
+    if (max_degree < 2 || max_degree > RFR_MAX_DEGREE || (lanes != 1 && lanes != ROOT_LANES))
+        return hipErrorInvalidValue;
+    const int threads = (lanes * max_degree + 63) / 64 * 64;
+    hipLaunchKernelGGL(droots::k_roots, dim3(njobs), dim3(threads), 0, st, jobs_dev, njobs, lanes);
     return hipGetLastError();
 }
 
