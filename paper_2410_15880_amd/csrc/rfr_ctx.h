@@ -68,6 +68,7 @@ struct rfr_ctx {
     std::condition_variable cv_work, cv_slot;
     std::deque<rfr::Request *> queue;
     std::map<uint64_t, rfr::Request *> reqs;
+    int big_running = 0;         // admitted searches that fill the GPU on their own
     uint64_t next_ticket = 1;
     bool stopping = false;
     // ---- batch

@@ -17,13 +17,22 @@ namespace rfr {
 
 // Pick a free slot with room for `need` workspace bytes (growing or trading
 // workspaces of idle slots within the budget); blocks until possible.
-static Slot *acquire_slot(rfr_ctx *ctx, size_t need, rfr_status &st) {
+// A search with a half of at least 2^BIG_HALF keys fills the GPU by itself:
+// two of them side by side would each take about twice as long, so such
+// searches are admitted one at a time (smaller ones still run beside them).
+constexpr int BIG_HALF = 23;
+
+static Slot *acquire_slot(rfr_ctx *ctx, size_t need, bool big, rfr_status &st) {
     std::unique_lock<std::mutex> lk(ctx->mu);
     if (need > ctx->budget) {
         st = fail(RFR_ENOMEM, "request tables exceed the memory budget");
         return nullptr;
     }
     for (;;) {
+        if (big && ctx->big_running > 0) {
+            ctx->cv_slot.wait(lk);
+            continue;
+        }
         Slot *best = nullptr;
         for (auto &s : ctx->slots) {
             if (s.busy) continue;
@@ -67,6 +76,7 @@ static Slot *acquire_slot(rfr_ctx *ctx, size_t need, rfr_status &st) {
         }
         if (best) {
             best->busy = true;
+            if (big) ++ctx->big_running;
             st = RFR_OK;
             return best;
         }
@@ -81,10 +91,11 @@ static Slot *acquire_slot(rfr_ctx *ctx, size_t need, rfr_status &st) {
     }
 }
 
-static void release_slot(rfr_ctx *ctx, Slot *s) {
+static void release_slot(rfr_ctx *ctx, Slot *s, bool big) {
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
         s->busy = false;
+        if (big) --ctx->big_running;
     }
     ctx->cv_slot.notify_all();
 }
@@ -112,12 +123,15 @@ static rfr_status serve_poly(rfr_ctx *ctx, RootBuf &rb, const int64_t *coeffs, i
             // streamed) when the full tables would take over half the budget
             size_t need = recombine_workspace(P.n);
             if (need > ctx->budget / 2) need = choose_workspace(P.n, ctx->budget / 2);
-            Slot *s = need ? acquire_slot(ctx, need, st) : nullptr;
+            int na, nb;
+            split_halves(P.n, na, nb);
+            const bool big = na >= BIG_HALF;
+            Slot *s = need ? acquire_slot(ctx, need, big, st) : nullptr;
             if (!need) st = fail(RFR_ENOMEM, "request tables do not fit the memory budget");
             if (s) {
                 t1 = now_ms();
                 st = search_on_slot(ctx, *s, P, cands);
-                release_slot(ctx, s);
+                release_slot(ctx, s, big);
             }
         }
         t2 = now_ms();
