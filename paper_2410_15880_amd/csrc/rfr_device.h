@@ -21,9 +21,10 @@ constexpr int TILES1 = 8;         // tiles per K0/K1 workgroup
 constexpr int MAXB1_LOG = 11;     // level-1 digit bits (buckets) at most
 constexpr int MAXB1 = 1 << MAXB1_LOG;
 // ---- K2: per-bucket tile sort by the level-2 digit
-constexpr int NT2 = 512;
-constexpr int T2 = 4096;          // keys per tile (<= 65535: u16 digit offsets)
-constexpr int KPT2 = T2 / NT2;
+constexpr int KPT2 = 8;           // keys per K2 thread
+constexpr int T2_LOG = 12;        // level-2 tile of 2^12 keys (512-thread K2 workgroups)
+constexpr int T2_BIG_LOG = 13;    // 2^13 keys (1024 threads) for one search with long level-1 buckets
+                                  // (tiles <= 65535 keys: u16 digit offsets)
 constexpr int MAXB2_LOG = 12;
 constexpr int MAXB2 = 1 << MAXB2_LOG;
 // ---- K3: sub-bucket gather, LDS radix sort of B', band join probing it with A
@@ -60,6 +61,7 @@ struct HalfArgs {
     uint32_t nwg1;       // K0/K1/K4 workgroups
     uint32_t ntile2_max; // level-2 tile capacity
     int m, L;            // weights in this half, lane bits
+    int t2log;           // level-2 tile = 2^t2log keys
 };
 
 struct JobArgs {
@@ -116,6 +118,7 @@ struct JobPlan {
     int nhalves = 2;
     HalfPlan h[2];
     int B1 = 0, B2 = 0;
+    int t2log = dev::T2_LOG;
     uint64_t kcap = dev::KCAP_MAX;
     uint64_t *kp = nullptr, *rec = nullptr, *counters = nullptr;
 };
@@ -124,7 +127,7 @@ struct JobPlan {
 struct MultiLaunch {
     std::vector<dev::JobArgs> jobs;
     std::vector<std::vector<uint32_t>> bases;  // [stage][job + 1]
-    int maxB1 = 0, maxB2 = 0;
+    int maxB1 = 0, maxB2 = 0, maxT2 = dev::T2_LOG;
     void add(const JobPlan &P, const dev::JobArgs &J);
     // bases, then the per-stage block -> job tables (bytes; see Multi)
     size_t bases_bytes() const;

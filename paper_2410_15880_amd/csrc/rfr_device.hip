@@ -343,7 +343,7 @@ __global__ __launch_bounds__(NT1) void k_scan_buckets(JobArgs Jarg, Multi M) {
     for (int base = 0; base < nb; base += NT1) {
         const int i = base + threadIdx.x;
         const uint64_t v = i < nb ? H.bstart[i] : 0;
-        const uint64_t nt = (v + T2 - 1) / T2;
+        const uint64_t nt = (v + ((uint64_t)1 << H.t2log) - 1) >> H.t2log;
         uint64_t tot, ttot;
         const uint64_t ex = block_excl_scan<NT1>(v, s_tmp, &tot);
         const uint64_t tex = block_excl_scan<NT1>(nt, s_tmp, &ttot);
@@ -361,11 +361,12 @@ __global__ __launch_bounds__(NT1) void k_scan_buckets(JobArgs Jarg, Multi M) {
 }
 
 // ------------------------------------------------------------------ K2
-// One tile (<= T2 keys) of one level-1 bucket: counting sort by the level-2
-// digit in LDS, written back in place; digstart[d][tile] = offset of digit d
-// inside the tile, digstart[nd][tile] = tile length.
-template <int NBMAX, bool MULTI>
-__global__ __launch_bounds__(NT2) void k_tile2(JobArgs Jarg, Multi M) {
+// One tile (<= NT*KPT2 = 2^t2log keys) of one level-1 bucket: counting sort by
+// the level-2 digit in LDS, written back in place; digstart[d][tile] = offset
+// of digit d inside the tile, digstart[nd][tile] = tile length.
+template <int NBMAX, int NT, bool MULTI>
+__global__ __launch_bounds__(NT) void k_tile2(JobArgs Jarg, Multi M) {
+    constexpr int TT = NT * KPT2;
     const JobArgs *Jp;
     uint32_t tile;
     if (!pick<MULTI>(Jarg, M, ST_TILE2, Jp, tile)) return;
@@ -379,10 +380,10 @@ __global__ __launch_bounds__(NT2) void k_tile2(JobArgs Jarg, Multi M) {
     const uint32_t m2 = (uint32_t)nd - 1;
     const int tid = threadIdx.x;
 
-    __shared__ uint64_t s_buf[T2];
+    __shared__ uint64_t s_buf[TT];
     __shared__ uint32_t s_cnt[NBMAX];
     __shared__ uint32_t s_off[NBMAX];
-    __shared__ uint64_t s_tmp[NT2 / 64 + 1];
+    __shared__ uint64_t s_tmp[NT / 64 + 1];
     __shared__ int s_b;
 
     if (tid == 0) {
@@ -394,11 +395,11 @@ __global__ __launch_bounds__(NT2) void k_tile2(JobArgs Jarg, Multi M) {
         }
         s_b = lo;
     }
-    for (int d = tid; d < nd; d += NT2) s_cnt[d] = 0;
+    for (int d = tid; d < nd; d += NT) s_cnt[d] = 0;
     __syncthreads();
     const int b = s_b;
-    const uint64_t base = H.bstart[b] + (uint64_t)(tile - H.tstart[b]) * T2;
-    const int len = (int)min((uint64_t)T2, H.bstart[b + 1] - base);
+    const uint64_t base = H.bstart[b] + ((uint64_t)(tile - H.tstart[b]) << H.t2log);
+    const int len = (int)min((uint64_t)1 << H.t2log, H.bstart[b + 1] - base);  // <= TT by the launch
     uint64_t *const keys = H.keys + base;  // a local: stores must not force reloads of the argument block
 
     uint64_t key[KPT2];
@@ -406,31 +407,31 @@ __global__ __launch_bounds__(NT2) void k_tile2(JobArgs Jarg, Multi M) {
     // all loads first (independent, in flight together), then the ranks
 #pragma unroll
     for (int k = 0; k < KPT2; ++k) {
-        const int p = tid + k * NT2;
+        const int p = tid + k * NT;
         if (p < len) key[k] = __builtin_nontemporal_load(&keys[p]);
     }
 #pragma unroll
     for (int k = 0; k < KPT2; ++k) {
-        const int p = tid + k * NT2;
+        const int p = tid + k * NT;
         if (p < len) rank[k] = atomicAdd(&s_cnt[dig(key[k], sh2, m2)], 1u);
     }
     __syncthreads();
-    for (int d = tid; d < nd; d += NT2) s_off[d] = s_cnt[d];
+    for (int d = tid; d < nd; d += NT) s_off[d] = s_cnt[d];
     __syncthreads();
-    lds_excl_scan<NT2, (NBMAX + NT2 - 1) / NT2>(s_off, nd, s_tmp);
+    lds_excl_scan<NT, (NBMAX + NT - 1) / NT>(s_off, nd, s_tmp);
 #pragma unroll
     for (int k = 0; k < KPT2; ++k) {
-        const int p = tid + k * NT2;
+        const int p = tid + k * NT;
         if (p < len) s_buf[s_off[dig(key[k], sh2, m2)] + rank[k]] = key[k];
     }
     __syncthreads();
     uint64_t kv[KPT2];
 #pragma unroll
-    for (int k = 0; k < KPT2; ++k) kv[k] = s_buf[tid + k * NT2];
+    for (int k = 0; k < KPT2; ++k) kv[k] = s_buf[tid + k * NT];
 #pragma unroll
     for (int k = 0; k < KPT2; ++k)
-        if (tid + k * NT2 < len) keys[tid + k * NT2] = kv[k];
-    for (int d = tid; d < nd; d += NT2) H.digstart[(size_t)d * H.ntile2_max + tile] = (uint16_t)s_off[d];
+        if (tid + k * NT < len) keys[tid + k * NT] = kv[k];
+    for (int d = tid; d < nd; d += NT) H.digstart[(size_t)d * H.ntile2_max + tile] = (uint16_t)s_off[d];
     if (tid == 0) H.digstart[(size_t)nd * H.ntile2_max + tile] = (uint16_t)len;
 }
 
@@ -456,7 +457,7 @@ __device__ __forceinline__ void for_each_global(const HalfArgs &H, int B2, int b
     for (uint32_t t = r.t0; t < r.t1; ++t) {
         const uint32_t s = H.digstart[(size_t)d * H.ntile2_max + t];
         const uint32_t e = H.digstart[(size_t)(d + 1) * H.ntile2_max + t];
-        const uint64_t tb = r.pos0 + (uint64_t)(t - r.t0) * T2;
+        const uint64_t tb = r.pos0 + ((uint64_t)(t - r.t0) << H.t2log);
         for (uint32_t q = s; q < e; ++q)
             if (!f(H.keys[tb + q])) return;
     }
@@ -565,7 +566,7 @@ __device__ __forceinline__ void gather_regs(const JobArgs &J, int d, const SubRe
             const uint32_t pos = base[h] + (h ? (uint32_t)(pre_off >> 32) : (uint32_t)pre_off);
             if (len[h] > 0) {
                 if (pos < CAP3) s_map[h * CAP3 + pos] = (uint8_t)tid;
-                s_src[h][tid] = (c0 + tid) * (uint32_t)T2 + st[h] - pos;
+                s_src[h][tid] = ((c0 + tid) << J.h[h].t2log) + st[h] - pos;
             }
         }
         __syncthreads();
@@ -668,7 +669,7 @@ __device__ void join_fallback(const JobArgs &J, uint32_t s, uint32_t NS, int b, 
     for (uint32_t t = ra.t0; t < ra.t1; ++t) {
         const uint32_t st = HA.digstart[(size_t)d * HA.ntile2_max + t];
         const uint32_t en = HA.digstart[(size_t)(d + 1) * HA.ntile2_max + t];
-        const uint64_t tb = ra.pos0 + (uint64_t)(t - ra.t0) * T2;
+        const uint64_t tb = ra.pos0 + ((uint64_t)(t - ra.t0) << HA.t2log);
         for (uint32_t q = st + threadIdx.x; q < en; q += NT3) {
             const uint64_t a = HA.keys[tb + q];
             for (int k = 0; k < nn; ++k) {
@@ -1357,7 +1358,7 @@ static uint64_t layout(JobPlan &P, char *base) {
     const int nb = 1 << P.B1, nd = 1 << P.B2;
     for (int k = 0; k < P.nhalves; ++k) {
         HalfPlan &h = P.h[k];
-        h.ntile2_max = (uint32_t)(h.N / T2 + nb + 1);
+        h.ntile2_max = (uint32_t)((h.N >> P.t2log) + nb + 1);
         h.a.keys = (uint64_t *)take(h.N * 8);
         h.a.hist1 = (uint64_t *)take((uint64_t)nb * h.nwg1 * 8);
         h.a.bstart = (uint64_t *)take((uint64_t)(nb + 1) * 8);
@@ -1370,6 +1371,7 @@ static uint64_t layout(JobPlan &P, char *base) {
         h.a.ntile2_max = h.ntile2_max;
         h.a.m = h.m;
         h.a.L = h.L;
+        h.a.t2log = P.t2log;
     }
     P.kp = (uint64_t *)take(P.kcap * 16);
     P.rec = (uint64_t *)take(2ull * P.kcap * 16);
@@ -1388,6 +1390,10 @@ uint64_t plan_job(int na, int nb, JobPlan &P, uint64_t kcap, bool batch) {
         nmax = std::max(nmax, P.h[1].N);
     }
     plan_bits(nmax, batch, P.B1, P.B2);
+    // One search whose level-1 buckets average four or more 2^13-key tiles
+    // takes them: half as many tile segments per sub-bucket for K3 to gather.
+    // A batch keeps the smaller tiles (its buckets hold a few partial ones).
+    if (!batch && (nmax >> P.B1) >= (1ull << (T2_BIG_LOG + 2))) P.t2log = T2_BIG_LOG;
     return layout(P, nullptr);
 }
 
@@ -1442,7 +1448,8 @@ void stage_blocks(const JobPlan &P, uint32_t *x) {
 // stage is grids[stage] and the per-job block offsets live in M.bases.
 template <bool MULTI>
 static hipError_t launch_all(const JobArgs &J, const Multi &M, const uint32_t *grids, int nh, int maxB1,
-                             int maxB2, bool search, uint64_t *sorted, hipStream_t st, StageEvents *ev) {
+                             int maxB2, int maxT2, bool search, uint64_t *sorted, hipStream_t st,
+                             StageEvents *ev) {
     auto rec = [&](int i) {
         if (ev && ev->ev[i]) (void)hipEventRecord((hipEvent_t)ev->ev[i], st);
     };
@@ -1459,9 +1466,18 @@ static hipError_t launch_all(const JobArgs &J, const Multi &M, const uint32_t *g
     else if (maxB1 <= 10) hipLaunchKernelGGL((k_enum<false, 1024, MULTI>), dim3(grids[ST_ENUM], nh), dim3(NT1), 0, st, J, M);
     else hipLaunchKernelGGL((k_enum<false, MAXB1, MULTI>), dim3(grids[ST_ENUM], nh), dim3(NT1), 0, st, J, M);
     rec(3);
-    if (maxB2 <= 8) hipLaunchKernelGGL((k_tile2<256, MULTI>), dim3(grids[ST_TILE2], nh), dim3(NT2), 0, st, J, M);
-    else if (maxB2 <= 10) hipLaunchKernelGGL((k_tile2<1024, MULTI>), dim3(grids[ST_TILE2], nh), dim3(NT2), 0, st, J, M);
-    else hipLaunchKernelGGL((k_tile2<MAXB2, MULTI>), dim3(grids[ST_TILE2], nh), dim3(NT2), 0, st, J, M);
+    // the workgroup holds the launch's largest tile (a job's tiles may be smaller)
+    if (maxT2 > T2_LOG) {
+        constexpr int NT = (1 << T2_BIG_LOG) / KPT2;
+        if (maxB2 <= 8) hipLaunchKernelGGL((k_tile2<256, NT, MULTI>), dim3(grids[ST_TILE2], nh), dim3(NT), 0, st, J, M);
+        else if (maxB2 <= 10) hipLaunchKernelGGL((k_tile2<1024, NT, MULTI>), dim3(grids[ST_TILE2], nh), dim3(NT), 0, st, J, M);
+        else hipLaunchKernelGGL((k_tile2<MAXB2, NT, MULTI>), dim3(grids[ST_TILE2], nh), dim3(NT), 0, st, J, M);
+    } else {
+        constexpr int NT = (1 << T2_LOG) / KPT2;
+        if (maxB2 <= 8) hipLaunchKernelGGL((k_tile2<256, NT, MULTI>), dim3(grids[ST_TILE2], nh), dim3(NT), 0, st, J, M);
+        else if (maxB2 <= 10) hipLaunchKernelGGL((k_tile2<1024, NT, MULTI>), dim3(grids[ST_TILE2], nh), dim3(NT), 0, st, J, M);
+        else hipLaunchKernelGGL((k_tile2<MAXB2, NT, MULTI>), dim3(grids[ST_TILE2], nh), dim3(NT), 0, st, J, M);
+    }
     rec(4);
     if (!search) {
         hipLaunchKernelGGL((k_join<true, MULTI>), dim3(grids[ST_JOIN]), dim3(NT3), 0, st, J, M, sorted);
@@ -1557,7 +1573,7 @@ rfr_status enqueue_recombine(const uint64_t *w, int n, uint64_t t_lo, uint64_t t
         J.first_chunk = t == 0;
         // half B' is enumerated, partitioned and tile-sorted by the first chunk
         // only; later chunks redo half A and join against the resident B'
-        if (launch_all<false>(J, M, grids, t == 0 ? 2 : 1, P.B1, P.B2, true, nullptr, st,
+        if (launch_all<false>(J, M, grids, t == 0 ? 2 : 1, P.B1, P.B2, P.t2log, true, nullptr, st,
                               nchunks == 1 ? ev : nullptr) != hipSuccess) {
             err = "kernel launch failed";
             return RFR_EDEVICE;
@@ -1601,7 +1617,7 @@ rfr_status enqueue_expand(const uint64_t *w, int m, int negate, void *ws, size_t
     uint32_t grids[NSTAGES];
     stage_blocks(P, grids);
     Multi M{};
-    if (launch_all<false>(J, M, grids, 1, P.B1, P.B2, false, sorted, st, nullptr) != hipSuccess) {
+    if (launch_all<false>(J, M, grids, 1, P.B1, P.B2, P.t2log, false, sorted, st, nullptr) != hipSuccess) {
         err = "kernel launch failed";
         return RFR_EDEVICE;
     }
@@ -1617,6 +1633,7 @@ void MultiLaunch::add(const JobPlan &P, const JobArgs &J) {
     jobs.push_back(J);
     maxB1 = std::max(maxB1, P.B1);
     maxB2 = std::max(maxB2, P.B2);
+    maxT2 = std::max(maxT2, P.t2log);
 }
 
 // Entries of each stage's block -> job table (see pick()).
@@ -1663,7 +1680,7 @@ hipError_t MultiLaunch::launch(const JobArgs *jobs_dev, const uint32_t *bases_de
     uint32_t grids[NSTAGES];
     for (int s = 0; s < NSTAGES; ++s) grids[s] = bases[s].back();
     JobArgs dummy{};
-    return launch_all<true>(dummy, M, grids, 2, maxB1, maxB2, true, nullptr, st, ev);
+    return launch_all<true>(dummy, M, grids, 2, maxB1, maxB2, maxT2, true, nullptr, st, ev);
 }
 
 // ---------------------------------------------------------------- small searches

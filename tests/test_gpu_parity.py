@@ -55,7 +55,7 @@ def planted_weights(rng, n, k_rel=2):
 # ------------------------------------------------------------------ EXPAND
 
 
-@pytest.mark.parametrize("m", [1, 3, 7, 8, 9, 12, 15, 19, 22])
+@pytest.mark.parametrize("m", [1, 3, 7, 8, 9, 12, 15, 19, 22, 24])
 @pytest.mark.parametrize("negate", [False, True])
 def test_expand_matches_sorted_subset_sums(R, m, negate):
     rng = random.Random(100 + m)
@@ -88,7 +88,7 @@ def test_search_matches_bruteforce(R, n):
         assert got == want
 
 
-@pytest.mark.parametrize("n", [30, 33, 38])
+@pytest.mark.parametrize("n", [30, 33, 38, 49])
 def test_search_matches_hs_oracle(R, n):
     rng = random.Random(1000 + n)
     w = planted_weights(rng, n, k_rel=4)
