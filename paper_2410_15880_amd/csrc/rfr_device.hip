@@ -374,6 +374,16 @@ __global__ __launch_bounds__(NT) void k_tile2(JobArgs Jarg, Multi M) {
     const HalfArgs &H = J.h[blockIdx.y];
     const int nb = 1 << J.B1;
     const uint32_t ntiles = H.tstart[nb];
+    if (!MULTI) {
+        // Consecutive tiles on one XCD (workgroups are dealt out to the 8 XCDs
+        // in turn): tile t's digit offsets sit beside tile t+1's in every row
+        // of digstart, so the rows' cache lines fill in one L2 instead of
+        // reaching memory as many 2-byte partial writes.  The grid is a
+        // multiple of 8 and at least 8 * ceil(ntiles / 8).
+        const uint32_t chunk = (ntiles + 7) >> 3;
+        if ((tile >> 3) >= chunk) return;
+        tile = (tile & 7) * chunk + (tile >> 3);
+    }
     if (tile >= ntiles) return;
     const int nd = 1 << J.B2;
     const int sh2 = 64 - J.B1 - J.B2;
@@ -1559,6 +1569,7 @@ rfr_status enqueue_recombine(const uint64_t *w, int n, uint64_t t_lo, uint64_t t
     for (int i = 0; i < nb; ++i) wneg[i] = 0 - w[na + i];
     uint32_t grids[NSTAGES];
     stage_blocks(P, grids);
+    grids[ST_TILE2] = (grids[ST_TILE2] + 7) & ~7u;  // single launch: K2 deals tiles to XCDs in 8 ranges
     Multi M{};
     const uint64_t nchunks = 1ull << c;
     for (uint64_t t = 0; t < nchunks; ++t) {
@@ -1616,6 +1627,7 @@ rfr_status enqueue_expand(const uint64_t *w, int m, int negate, void *ws, size_t
     J.kcap = 1;
     uint32_t grids[NSTAGES];
     stage_blocks(P, grids);
+    grids[ST_TILE2] = (grids[ST_TILE2] + 7) & ~7u;  // single launch: K2 deals tiles to XCDs in 8 ranges
     Multi M{};
     if (launch_all<false>(J, M, grids, 1, P.B1, P.B2, P.t2log, false, sorted, st, nullptr) != hipSuccess) {
         err = "kernel launch failed";
