@@ -438,9 +438,12 @@ __global__ __launch_bounds__(NT) void k_tile2(JobArgs Jarg, Multi M) {
     uint64_t kv[KPT2];
 #pragma unroll
     for (int k = 0; k < KPT2; ++k) kv[k] = s_buf[tid + k * NT];
+    // streaming stores: the tile is written whole (K1's partial lines are
+    // merged in L2 at its seams; K2 has none) and is next read by K3, long
+    // after it would have left the caches
 #pragma unroll
     for (int k = 0; k < KPT2; ++k)
-        if (tid + k * NT < len) keys[tid + k * NT] = kv[k];
+        if (tid + k * NT < len) __builtin_nontemporal_store(kv[k], &keys[tid + k * NT]);
     for (int d = tid; d < nd; d += NT) H.digstart[(size_t)d * H.ntile2_max + tile] = (uint16_t)s_off[d];
     if (tid == 0) H.digstart[(size_t)nd * H.ntile2_max + tile] = (uint16_t)len;
 }
