@@ -283,13 +283,29 @@ __global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
         for (int i0 = 0; i0 < KPT1; i0 += 8) {
             uint64_t kv[8], dst[8];
+            bool inner[8];
 #pragma unroll
             for (int i = 0; i < 8; ++i) kv[i] = s_buf[tid + (i0 + i) * NT1];
+            // a key whose 128-byte line lies inside its run [g0, g1) (all 16
+            // keys of the line come from this store phase) is streamed out;
+            // the run's end lines, shared with other workgroups' runs, are
+            // merged in L2 first
 #pragma unroll
-            for (int i = 0; i < 8; ++i) dst[i] = s_cur[dig(kv[i], sh1, m1)] + (uint64_t)(tid + (i0 + i) * NT1);
+            for (int i = 0; i < 8; ++i) {
+                const uint32_t d = dig(kv[i], sh1, m1);
+                const uint64_t c = s_cur[d];
+                const uint64_t g0 = c + s_off[d];
+                const uint64_t g1 = g0 + s_cnt[d];
+                dst[i] = c + (uint64_t)(tid + (i0 + i) * NT1);
+                const uint64_t l0 = dst[i] & ~(uint64_t)15;
+                inner[i] = l0 >= g0 && l0 + 16 <= g1;
+            }
 #pragma unroll
             for (int i = 0; i < 8; ++i)
-                if (tid + (i0 + i) * NT1 < tile) keys_out[dst[i]] = kv[i];
+                if (tid + (i0 + i) * NT1 < tile) {
+                    if (inner[i]) __builtin_nontemporal_store(kv[i], &keys_out[dst[i]]);
+                    else keys_out[dst[i]] = kv[i];
+                }
         }
         __syncthreads();
         for (int b = tid; b < nb; b += NT1) {
