@@ -148,7 +148,10 @@ static rfr_status device_roots(BatchState *B, hipStream_t st, std::vector<Prepar
     int dmax = 2;
     for (int i : jobs) dmax = std::max(dmax, (int)P[i].prim.size() - 1);
     bool ok = hipMemcpyAsync(B->rdev, B->rhost, o_out, hipMemcpyHostToDevice, st) == hipSuccess;
-    ok = ok && launch_roots((const RootJob *)(B->rdev + o_jobs), (int)jobs.size(), dmax, 1, st) == hipSuccess;
+    // up to one polynomial per CU: ROOT_LANES lanes per root (shorter dependent
+    // chains); beyond that one lane per root keeps more polynomials in flight
+    const int lanes = jobs.size() <= 256 ? ROOT_LANES : 1;
+    ok = ok && launch_roots((const RootJob *)(B->rdev + o_jobs), (int)jobs.size(), dmax, lanes, st) == hipSuccess;
     ok = ok && hipMemcpyAsync(B->rhost + o_out, B->rdev + o_out, nro * sizeof(RootOut), hipMemcpyDeviceToHost,
                               st) == hipSuccess;
     ok = ok && hipStreamSynchronize(st) == hipSuccess;
