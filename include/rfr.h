@@ -82,9 +82,12 @@ typedef struct rfr_result {
     uint64_t n_candidates;     /* candidate patterns the search returned */
     uint64_t n_confirmed;      /* candidates that divide p exactly */
     uint64_t t_lo, t_hi;       /* accept window: sum in [2^64 - t_lo, 2^64) U [0, t_hi] */
-    double ms_roots;           /* host time: roots, weights, window */
-    double ms_search;          /* recombination search (device) */
-    double ms_confirm;         /* host time: confirmation and atoms */
+    double ms_roots;           /* wall time of normalisation, roots (device, or host when the
+                                  device roots fail a check), single-element factors, weights
+                                  and window */
+    double ms_search;          /* wall time of the recombination search (device) and the
+                                  candidate copy back */
+    double ms_confirm;         /* wall time on the host: confirmation and atoms */
 } rfr_result;
 
 /* ------------------------------------------------------------------ context */
@@ -117,10 +120,17 @@ rfr_status rfr_factor(rfr_ctx *ctx, const int64_t *coeffs, int degree, rfr_resul
  * coeffs: all polynomials concatenated, polynomial i occupying
  *         coeffs[off_i .. off_i + degrees[i]], off_i = sum_{k<i}(degrees[k]+1).
  * out[i] receives a result (or NULL on failure) and status[i] its status.
- * The roots run on a host thread pool; the searches of all polynomials run in
- * one persistent kernel launch (one workgroup per polynomial, largest first),
- * replayed from a captured HIP graph.  Returns RFR_OK if the batch ran, even
- * when some entries failed (see status[]). */
+ * The roots of all polynomials are found in one device launch (a workgroup
+ * per polynomial); elements, weights and window on a host thread pool.  The
+ * searches are split by size: those whose halves hold at most 2^11 keys run
+ * in one persistent kernel (a workgroup per search, taken largest first from
+ * an atomic queue, everything in LDS); mid-size ones run through the staged
+ * pipeline with one launch per stage for all of them; searches with a half of
+ * 2^23 keys or more (each fills the GPU) are queued one after another.  The
+ * device pass of the small and mid searches is captured once per batch shape
+ * into a HIP graph and replayed.  Confirmation runs on the thread pool.
+ * Returns RFR_OK if the batch ran, even when some entries failed (see
+ * status[]). */
 rfr_status rfr_factor_batch(rfr_ctx *ctx, int count, const int64_t *coeffs,
                             const int32_t *degrees, rfr_result **out, rfr_status *status);
 
@@ -279,8 +289,12 @@ size_t rfr_expand_workspace_bytes(int m);
 /*
  * EXPAND (Section 3.3): the 2^m subset sums of m weights (negated first when
  * `negate` is nonzero), sorted ascending, written to sorted_dev[2^m].
- * Same kernels as the search (enumerate, partition, tile sort, final sort).
- * Requires 1 <= m <= 30.  Enqueue only, like rfr_recombine_dev.
+ * Same kernels as the search (enumerate, partition, tile sort, final sort in
+ * LDS).  Requires 1 <= m <= 30 (else RFR_EINVAL).  Synchronises hip_stream
+ * before returning: the final sort holds at most 2048 keys sharing their top
+ * partition bits, and sums more clustered than that (many equal sums, such as
+ * from zero or repeated weights) return RFR_EOVERFLOW with sorted_dev only
+ * partly written.
  */
 rfr_status rfr_expand_dev(const uint64_t *w_host, int m, int negate, void *workspace,
                           size_t ws_bytes, void *hip_stream, uint64_t *sorted_dev);

@@ -73,7 +73,7 @@ struct JobArgs {
     uint64_t *kp_count;
     uint64_t kcap;
     uint64_t *rec;              // [2][kcap][2] (key, pattern) per half
-    uint32_t *rec_count;        // [2]
+    uint64_t *rec_count;        // [2]
     uint64_t *out;              // [2*cap] pattern pairs
     uint64_t *out_count;
     uint64_t cap;

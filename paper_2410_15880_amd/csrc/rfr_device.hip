@@ -16,10 +16,14 @@
 //   K2 k_tile2        LDS counting sort of each bucket tile by the level-2
 //                     digit, written back in place + per-digit tile offsets
 //   K3 k_join         per sub-bucket (level-1 + level-2 prefix): gather both
-//                     halves, LDS radix sort on the next digit + insertion,
-//                     merge-path band join emitting every key pair in window
-//   K4 k_recover      compute-only re-enumeration mapping candidate keys back
-//                     to patterns
+//                     halves into registers, semi-join through LDS cell
+//                     bitmaps (B' marks cells, A keys meeting a marked cell
+//                     and the B' keys in their cells form two short lists),
+//                     exact test of every list pair; every key pair in the
+//                     window is emitted
+//   K4 k_recover_few  candidate keys back to patterns: a meet in the middle
+//      k_recover      inside each half (few keys), or a re-enumeration of
+//                     the half against an LDS bitmap of the keys (many)
 //   K5 k_pairs        one workgroup: de-duplicate key pairs, expand them into
 //                     pattern pairs
 // All arithmetic on keys is exact wrapping uint64.
@@ -1148,7 +1152,7 @@ __global__ __launch_bounds__(NT1) void k_recover_few(JobArgs Jarg, Multi M) {
             for (uint32_t c2 = 0; c2 < c && !dup; ++c2) dup = s_list[c2] == key;
             for (int q = lo; !dup && q < nl && s_sorted[q] == x; ++q) {
                 const uint64_t pat = ((uint64_t)s_lane[q] | (g << H.L)) | J.pbase[half];
-                const uint32_t r = atomicAdd(&J.rec_count[half], 1u);
+                const uint64_t r = atomicAdd((unsigned long long *)&J.rec_count[half], 1ull);
                 if (r < J.kcap) {
                     J.rec[((size_t)half * J.kcap + r) * 2] = key;
                     J.rec[((size_t)half * J.kcap + r) * 2 + 1] = pat;
@@ -1244,7 +1248,7 @@ __global__ __launch_bounds__(NT1) void k_recover(JobArgs Jarg, Multi M) {
                 }
                 if (lo < cnt && s_list[lo] == key) {
                     const uint64_t pat = ((uint64_t)tid | (g << H.L)) | J.pbase[half];
-                    const uint32_t r = atomicAdd(&J.rec_count[half], 1u);
+                    const uint64_t r = atomicAdd((unsigned long long *)&J.rec_count[half], 1ull);
                     if (r < J.kcap) {
                         J.rec[((size_t)half * J.kcap + r) * 2] = key;
                         J.rec[((size_t)half * J.kcap + r) * 2 + 1] = pat;
@@ -1275,11 +1279,14 @@ __global__ __launch_bounds__(NT1) void k_pairs(JobArgs Jarg, Multi M) {
     __shared__ uint64_t s_total;
     if (threadIdx.x == 0) s_total = carry;
     __syncthreads();
-    if (cnt > J.kcap || carry == ~0ull) {
+    // key pairs past the capacity, or (key, pattern) records of either half
+    // past it (many patterns sharing a candidate key), would lose pattern
+    // pairs: report the overflow instead
+    if (cnt > J.kcap || carry == ~0ull || J.rec_count[0] > J.kcap || J.rec_count[1] > J.kcap) {
         if (threadIdx.x == 0) *J.out_count = ~0ull;
         return;
     }
-    const uint32_t ra = min((uint64_t)J.rec_count[0], J.kcap), rb = min((uint64_t)J.rec_count[1], J.kcap);
+    const uint32_t ra = (uint32_t)min(J.rec_count[0], J.kcap), rb = (uint32_t)min(J.rec_count[1], J.kcap);
     for (uint32_t p = threadIdx.x; p < cnt; p += NT1) {
         const uint64_t a = J.kp[2 * p], bk = J.kp[2 * p + 1];
         bool first = true;
@@ -1441,7 +1448,7 @@ void build_job(JobPlan &P, char *ws, const uint64_t *wa, const uint64_t *wb, uin
     J.kp = P.kp;
     J.kp_count = P.counters;
     J.rec = P.rec;
-    J.rec_count = (uint32_t *)(P.counters + 1);
+    J.rec_count = P.counters + 3;
     J.flags = (uint32_t *)(P.counters + 2);
     J.kcap = P.kcap;
     J.t_lo = t_lo;
@@ -1651,6 +1658,19 @@ rfr_status enqueue_expand(const uint64_t *w, int m, int negate, void *ws, size_t
     if (launch_all<false>(J, M, grids, 1, P.B1, P.B2, P.t2log, false, sorted, st, nullptr) != hipSuccess) {
         err = "kernel launch failed";
         return RFR_EDEVICE;
+    }
+    // A sub-bucket beyond the LDS sort's capacity (more than CAP3 keys share
+    // their top B1 + B2 bits: many equal or clustered sums) is left unsorted
+    // and flagged; report it rather than return a partly written output.
+    uint32_t flags = 0;
+    if (hipMemcpyAsync(&flags, J.flags, sizeof(flags), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        err = "rfr_expand_dev: device error";
+        return RFR_EDEVICE;
+    }
+    if (flags & 1u) {
+        err = "rfr_expand_dev: the sums are too clustered for the sort (a sub-bucket holds more than 2048 keys)";
+        return RFR_EOVERFLOW;
     }
     return RFR_OK;
 }

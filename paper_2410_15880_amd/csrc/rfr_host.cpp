@@ -489,6 +489,12 @@ static rfr_status weights_window(Prepared &P, std::string &err) {
         return RFR_EPRECISION;
     }
     uint64_t E = (uint64_t)std::ceil(Ed) + 2 * (uint64_t)P.n + 2;
+    // the search takes windows with t_lo + t_hi < 2^32 (a cell of its join is
+    // at least that wide); a wider one means the roots are not precise enough
+    if ((uint64_t)P.n + 2 * E >= (1ull << 32)) {
+        err = "accept window too wide (roots not precise enough)";
+        return RFR_EPRECISION;
+    }
     P.t_lo = (uint64_t)P.n + E;
     P.t_hi = E;
     return RFR_OK;
@@ -732,14 +738,8 @@ rfr_status confirm_and_factor(const Prepared &P, const std::vector<Pat> &cands, 
         return e;
     };
     const dd a_d = dd_from_i64(P.prim[d]);
-    for (const Pat &s0 : cands) {
-        if (s0.empty()) continue;
-        Pat comp = full & ~s0;
-        if (found.count(s0)) continue;
-        bool small_is_s = deg_of(s0) <= deg_of(comp);
-        const Pat &side = small_is_s ? s0 : comp;
-        if (!traces_integral(P, side)) continue;
-        // a_d * prod over the side, in double-double
+    // a_d * prod over the side's roots (x - u) or (x^2 - 2 Re z x + |z|^2), in double-double
+    auto side_poly = [&](const Pat &side) {
         std::vector<dd> q{a_d};
         for (int i = 0; i < n; ++i) {
             if (!side.get(i)) continue;
@@ -762,6 +762,16 @@ rfr_status confirm_and_factor(const Prepared &P, const std::vector<Pat> &cands, 
             }
             q.swap(nq);
         }
+        return q;
+    };
+    for (const Pat &s0 : cands) {
+        if (s0.empty()) continue;
+        Pat comp = full & ~s0;
+        if (found.count(s0)) continue;
+        bool small_is_s = deg_of(s0) <= deg_of(comp);
+        const Pat &side = small_is_s ? s0 : comp;
+        if (!traces_integral(P, side)) continue;
+        const std::vector<dd> q = side_poly(side);
         std::vector<int64_t> f(q.size());
         bool ok = true;
         for (size_t k = 0; k < q.size() && ok; ++k) ok = round_dd(q[k], f[k]);
@@ -772,6 +782,19 @@ rfr_status confirm_and_factor(const Prepared &P, const std::vector<Pat> &cands, 
         bool ovf = false;
         if (!exact_div(P.prim, f, g, ovf)) {
             if (ovf) {
+                // For a true factor f the quotient is the cofactor a_d/lc(f) *
+                // prod over the other side, whose size the roots give.  If that
+                // cofactor fits int64 with room to spare (and f times it cannot
+                // reach the int128 limit of the division), a true division could
+                // not have overflowed: the candidate is not a factor.  Otherwise
+                // the factorisation may not be representable.
+                const Pat &other = small_is_s ? comp : s0;
+                const std::vector<dd> gq = side_poly(other);
+                double gmax = 0, fmax = 0;
+                const double scale = 1.0 / std::fabs((double)f.back());
+                for (const dd &c : gq) gmax = std::max(gmax, std::fabs(to_d(c)) * scale);
+                for (int64_t c : f) fmax = std::max(fmax, std::fabs((double)c));
+                if (gmax < std::ldexp(1.0, 62) && fmax * gmax * (double)f.size() < std::ldexp(1.0, 118)) continue;
                 err = "trial division overflowed int128";
                 return RFR_EOVERFLOW;
             }

@@ -1,6 +1,6 @@
 """Write expected factorisations for the seeded workloads using the oracle only.
 
-Usage:  python tests/golden/make_golden.py [large|mid|batch] ...
+Usage:  python tests/golden/make_golden.py [large|mid|batch|stream] ...
 
 Each output file maps the workload seed to the oracle's (content, factors) for
 that seeded input; nothing here touches the HIP library.
@@ -22,7 +22,7 @@ import workloads as W  # noqa: E402
 def _one(args):
     seed, coeffs = args
     t0 = time.time()
-    cont, facs = R.factor(coeffs)
+    cont, facs = R.factor_general(coeffs)
     return seed, {"coeffs": coeffs, "content": cont, "factors": [list(f) for f in facs],
                   "oracle_s": round(time.time() - t0, 2)}
 
@@ -34,12 +34,19 @@ def build(name):
         ws, procs = W.config_mid(), 6
     elif name == "batch":
         ws, procs = W.config_batch()[::32], 6
+    elif name == "stream":
+        # the served-mode test's requests (degrees up to 116) and the inputs
+        # with repeated factors that ride in the same stream; largest first,
+        # few at a time (the oracle's halves reach 2^29 sums)
+        ws = [r.work for r in W.config_stream(48, rate_per_s=400.0)] + W.config_repeated(6)
+        ws.sort(key=lambda w: -w.degree)
+        procs = 3
     else:
         raise SystemExit("unknown set " + name)
     jobs = [(w.seed, w.coeffs) for w in ws]
     with mp.Pool(procs) as pool:
         res = dict(pool.map(_one, jobs, chunksize=1))
-    out = {"_source": "oracle/rfr_ref.py factor() on workloads.config_%s" % name,
+    out = {"_source": "oracle/rfr_ref.py factor_general() on workloads.config_%s" % name,
            "cases": {str(k): res[k] for k in sorted(res)}}
     path = os.path.join(HERE, "golden_%s.json" % name)
     with open(path, "w") as f:

@@ -76,11 +76,39 @@ def test_batch_repeated_factors_match_oracle(R):
         assert got[2 * rep.index(w)] == O.factor_general(w.coeffs), w.seed
 
 
+def _sympy_factor(coeffs):
+    """(content, canonical factors) of sympy.factor_list (independent of RFR)."""
+    import sympy
+    from oracle import rfr_ref as O
+    X = sympy.Symbol("x")
+    c, fl = sympy.factor_list(sympy.Poly(list(reversed([int(v) for v in coeffs])), X))
+    c = int(c)
+    facs = []
+    for f, m in fl:
+        cs = [int(v) for v in reversed(f.all_coeffs())]
+        if cs[-1] < 0:
+            cs = [-v for v in cs]
+            c = -c if m % 2 else c
+        facs.extend([cs] * m)
+    return c, O.canonical(facs)
+
+
 def test_served_alone_equals_in_mix(R):
-    reqs = W.config_stream(48, rate_per_s=400.0, dcap=96)
-    # a few requests with repeated factors ride in the same stream
+    # the served stream's inputs: 48 Poisson requests (degrees log-uniform in
+    # [24, 128], coefficients in [-1000, 1000], 30 % planted), 6 inputs with
+    # repeated factors, and two of the largest size (degree 128: a random one
+    # and a 40 x 88 planted product, n about 65 -- 2^32-key halves that are
+    # admitted one at a time)
+    g = json.load(open(os.path.join(HERE, "golden", "golden_stream.json")))["cases"]
+    reqs = W.config_stream(48, rate_per_s=400.0)
     for i, w in enumerate(W.config_repeated(6)):
         reqs.insert(4 + 7 * i, W.Request(reqs[4 + 7 * i].t_arrive, w))
+    big = [W.Workload(W.rand_poly(W._rng(5901), 128, -1000, 1000), 5901, "random")]
+    rng = W._rng(5902)
+    f, h = W.rand_poly(rng, 40, -1000, 1000), W.rand_poly(rng, 88, -1000, 1000)
+    big.append(W.Workload(W.poly_mul(f, h), 5902, "planted", [f, h]))
+    reqs.insert(10, W.Request(reqs[10].t_arrive, big[0]))
+    reqs.insert(30, W.Request(reqs[30].t_arrive, big[1]))
     say("serving", len(reqs))
     with R.Context(0) as ctx:
         alone = [ctx.factor(r.work.coeffs) for r in reqs]
@@ -103,8 +131,22 @@ def test_served_alone_equals_in_mix(R):
             time.sleep(0.001)
         ctx.serve_stop()
     assert len(done) == len(tickets)
-    for t, a in zip(tickets, alone):
+    pinned = 0
+    for t, a, r in zip(tickets, alone, reqs):
         res, lat = done[t]
         assert not isinstance(res, Exception), res
-        assert (res["content"], res["factors"]) == a
+        got = (res["content"], res["factors"])
+        # the same alone and in the mix
+        assert got == a, r.work.seed
         assert lat >= 0
+        # and the oracle's (stored) or, beyond the oracle's reach, sympy's
+        e = g.get(str(r.work.seed))
+        if e is not None:
+            assert r.work.coeffs == e["coeffs"]
+            assert got == (e["content"], [tuple(x) for x in e["factors"]]), r.work.seed
+            pinned += 1
+        else:
+            assert r.work.seed in (5901, 5902)
+            say("  sympy factor_list, degree", r.work.degree)
+            assert got == _sympy_factor(r.work.coeffs), r.work.seed
+    assert pinned == len(reqs) - 2

@@ -74,6 +74,16 @@ def test_expand_duplicate_heavy(R):
     assert np.array_equal(R.expand_dev(w), O.expand(w))
 
 
+@pytest.mark.parametrize("m", [12, 14, 16])
+def test_expand_too_clustered_is_reported(R, m):
+    # 2^m equal sums exceed the final in-LDS sort (2048 keys per sub-bucket):
+    # an error, never a partly sorted output
+    say("expand zeros m=%d" % m)
+    with pytest.raises(R.RFRError) as e:
+        R.expand_dev([0] * m)
+    assert e.value.name == "RFR_EOVERFLOW"
+
+
 # ------------------------------------------------------------------ search
 
 
@@ -228,13 +238,56 @@ def test_chunked_search_matches_oracle(R, n, frac):
 
 
 def test_chunked_zero_weights_and_overflow(R):
+    # n = 27: halves of 13 weights, above the one-workgroup size, so a workspace
+    # between the minimum and the full one streams half A in chunks
     L = R.lib()
-    n = 12
+    n = 27
+    full = L.rfr_recombine_workspace_bytes(n)
     mn = L.rfr_recombine_min_workspace_bytes(n)
+    ws = (mn + full) // 2
+    assert mn <= ws < full
     say("chunked zeros")
-    assert R.recombine_dev([0] * n, 0, 0, cap=4096, ws_bytes=mn) == list(range(1, 1 << (n - 1)))
+    # all-zero weights: every pattern is a candidate, far past a small cap
     with pytest.raises(R.RFRError) as e:
-        R.recombine_dev([0] * n, 0, 0, cap=100, ws_bytes=mn)
+        R.recombine_dev([0] * n, 0, 0, cap=100, ws_bytes=ws)
+    assert e.value.name == "RFR_ECANDIDATES"
+    # a block of zero and of equal weights among random ones: every pattern
+    # duplicated over the zero block, equal sums from the repeated weight
+    rng = random.Random(2701)
+    w = planted_weights(rng, n, k_rel=3)
+    for i in (0, 5, 14, 20):
+        w[i] = 0
+    x = rng.getrandbits(64)
+    for i in (2, 9, 17):
+        w[i] = x
+    w[24] = (-2 * x) & MASK
+    say("chunked zero/equal block")
+    got = R.recombine_dev(w, n + 9, 6, cap=1 << 14, ws_bytes=ws)
+    assert got == O.search_hs(w, n + 9, 6)
+
+
+def test_many_patterns_per_candidate_key(R):
+    # half A = 13 equal weights x: the subsets of size k share the key k x.
+    # With half B holding -5x only, 1287 patterns of A pair with one B pattern:
+    # all must be returned.  With -5x, -6x and -7x the patterns of the
+    # candidate keys outnumber the 4096 (key, pattern) records a search holds,
+    # which must be reported as an overflow, never a partial answer.
+    rng = random.Random(4811)
+    x = rng.getrandbits(64)
+    base = [x] * 13 + [rng.getrandbits(64) for _ in range(13)] + [rng.getrandbits(64)]
+    w1 = list(base)
+    w1[13] = (-5 * x) & MASK
+    say("many patterns per key: one B pattern")
+    got = R.recombine_dev(w1, 30, 4, cap=1 << 16)
+    want = O.search_hs(w1, 30, 4)
+    assert len(want) >= 1287
+    assert got == want
+    w2 = list(w1)
+    w2[14] = (-6 * x) & MASK
+    w2[15] = (-7 * x) & MASK
+    say("many patterns per key: record overflow")
+    with pytest.raises(R.RFRError) as e:
+        R.recombine_dev(w2, 30, 4, cap=1 << 16)
     assert e.value.name == "RFR_ECANDIDATES"
 
 
@@ -356,8 +409,8 @@ def test_maximum_size_search_recovers_planted_factors(R):
     # degree-84 factors (coefficients in [-1000, 1000]) has n = 65 elements,
     # so both halves hold 2^32 keys (about 80 GB of tables): level-1 buckets
     # of more than one gather chunk, the many-candidate recovery, and every
-    # index past 32 bits.  The result must be the two drawn factors (random
-    # dense factors of this size are irreducible) and multiply back to p.
+    # index past 32 bits.  The result must be the two drawn factors, multiply
+    # back to p, and equal sympy's complete factorisation.
     rng = W._rng(9101)
     f = W.rand_poly(rng, 40, -1000, 1000)
     g = W.rand_poly(rng, 84, -1000, 1000)
@@ -372,3 +425,7 @@ def test_maximum_size_search_recovers_planted_factors(R):
     for q in r["factors"]:
         prod = O.poly_mul_exact(prod, list(q))
     assert prod == p
+    # the complete factorisation by a method independent of RFR (the oracle's
+    # search cannot reach n = 65): the two factors are irreducible
+    say("  sympy factor_list of the degree-%d product" % (len(p) - 1))
+    assert (r["content"], r["factors"]) == _sympy_factor(p)

@@ -243,3 +243,26 @@ def test_squarefree_large_multiplicity(R):
     for _ in range(4):
         p = O.poly_mul_exact(p, [1, 0, 1])
     assert R.squarefree(p) == O.squarefree(p) == (1, [((1, 0, 1), 4), ((-2, 3), 9)])
+
+
+def test_window_too_wide_for_the_search_is_a_precision_error(R):
+    # (a x - b)(a x - b - 1): two rational roots 1/a apart whose double-double
+    # inclusion radii grow like a, so the window grows like a^3 and crosses
+    # the search's limit (t_lo + t_hi < 2^32) between a = 2^19 and 2^20.
+    # Every a either gives a window the search accepts or RFR_EPRECISION
+    # (never a window that the search would reject as a bad argument).
+    seen_ok = seen_prec = 0
+    for k in range(400):
+        a = (1 << 19) + k * 1311
+        b = (a * 7) // 3
+        p = [b * (b + 1), -(2 * b + 1) * a, a * a]
+        try:
+            r = R.weights(p)
+        except R.RFRError as e:
+            assert e.name == "RFR_EPRECISION", (a, e)
+            seen_prec += 1
+            continue
+        assert r["t_lo"] + r["t_hi"] < (1 << 32), a
+        assert r["t_lo"] >= r["n"] + r["t_hi"]
+        seen_ok += 1
+    assert seen_ok > 0 and seen_prec > 0

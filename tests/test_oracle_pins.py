@@ -345,3 +345,43 @@ def test_squarefree_of_squarefree_input_is_itself():
 def test_factor_general_matches_sympy_factor_list():
     for w in W.config_repeated()[:12]:
         assert R.factor_general(w.coeffs) == sympy_factor(w.coeffs), w.seed
+
+
+# ---- real-root count (the r real elements of Eq 1) against exact isolation
+
+def _sympy_real_root_count(coeffs):
+    """Number of distinct real roots by sympy's exact real-root isolation
+    (continued-fraction bisection on the integer polynomial), a routine that
+    shares nothing with the oracle's numerical roots."""
+    return len(sympy.Poly(list(reversed([int(v) for v in coeffs])), X).intervals())
+
+
+def _oracle_real_count(coeffs):
+    cont, k, prim = R.normalise(coeffs)
+    reals, pairs, rr, rp = R.roots_hp(prim)
+    assert len(reals) + 2 * len(pairs) == len(prim) - 1
+    return len(reals) + (1 if k else 0)
+
+
+@pytest.mark.parametrize("which", ["mid", "batch", "large"])
+def test_real_root_count_matches_exact_isolation(which):
+    if which == "mid":
+        ws = W.config_mid()
+    elif which == "large":
+        ws = W.config_large()
+    else:
+        rnd = random.Random(17)
+        allw = W.config_batch()
+        ws = [allw[i] for i in rnd.sample(range(len(allw)), 24)]
+    for w in ws:
+        assert _oracle_real_count(w.coeffs) == _sympy_real_root_count(w.coeffs), w.seed
+
+
+# ---- stored expected results against sympy's factorisation
+
+@pytest.mark.parametrize("name", ["large", "batch", "mid"])
+def test_golden_files_match_sympy_factor_list(name):
+    g = json.load(open(os.path.join(HERE, "golden", "golden_%s.json" % name)))["cases"]
+    for seed, e in g.items():
+        want = sympy_factor(e["coeffs"])
+        assert (e["content"], [tuple(f) for f in e["factors"]]) == want, seed
