@@ -379,7 +379,7 @@ def test_real_root_count_matches_exact_isolation(which):
 
 # ---- stored expected results against sympy's factorisation
 
-@pytest.mark.parametrize("name", ["large", "batch", "mid"])
+@pytest.mark.parametrize("name", ["large", "batch", "mid", "stream"])
 def test_golden_files_match_sympy_factor_list(name):
     g = json.load(open(os.path.join(HERE, "golden", "golden_%s.json" % name)))["cases"]
     for seed, e in g.items():
