@@ -283,6 +283,28 @@ rfr_status rfr_recombine_dev(const uint64_t *w_host, int n, uint64_t t_lo, uint6
                              void *workspace, size_t ws_bytes, void *hip_stream,
                              uint64_t *cand_dev, uint64_t cap, uint64_t *count_dev);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the search
+ * of rfr_recombine_dev with the same arguments and results, minus the
+ * workspace, which is a fixed device array of
+ * rfr_recombine_noalloc_scratch_bytes() = 64 MiB inside the library (one per
+ * GPU, allocated with the library's code when it is first used on that GPU
+ * and held until the process ends).  The call allocates no device or host
+ * memory.  It searches up to n = 46 elements (larger n returns RFR_ENOMEM;
+ * from n = 45 on, half A is streamed in chunks as in rfr_recombine_dev with a
+ * small workspace).  hip_stream must belong to the current device.  All calls
+ * on one GPU share its scratch array: calls whose work overlaps on that GPU
+ * (other host threads, other streams) race and give wrong results; serialise
+ * them, e.g. on one stream.  The kernels clear every counter they use, so a
+ * call needs nothing cleared by the caller.
+ */
+rfr_status rfr_recombine_dev_noalloc(const uint64_t *w_host, int n, uint64_t t_lo, uint64_t t_hi,
+                                     void *hip_stream, uint64_t *cand_dev, uint64_t cap, uint64_t *count_dev);
+
+/* Size of the fixed device scratch of rfr_recombine_dev_noalloc. */
+size_t rfr_recombine_noalloc_scratch_bytes(void);
+
 /* Device workspace needed by rfr_expand_dev for m weights. */
 size_t rfr_expand_workspace_bytes(int m);
 

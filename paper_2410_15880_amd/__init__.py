@@ -32,7 +32,7 @@ EXPORTS = [
     "rfr_recombine_dev", "rfr_expand_workspace_bytes", "rfr_expand_dev",
     "rfr_profile", "rfr_profile_read", "rfr_recombine_min_workspace_bytes",
     "rfr_autotune", "rfr_load_tuning", "rfr_prepare_batch", "rfr_results_pack", "rfr_results_free",
-    "rfr_squarefree",
+    "rfr_squarefree", "rfr_recombine_dev_noalloc", "rfr_recombine_noalloc_scratch_bytes",
 ]
 
 
@@ -98,6 +98,8 @@ def lib():
         "rfr_recombine_workspace_bytes": ([C.c_int], sz),
         "rfr_recombine_min_workspace_bytes": ([C.c_int], sz),
         "rfr_recombine_dev": ([C.POINTER(u64), C.c_int, u64, u64, P, sz, P, P, u64, P], C.c_int),
+        "rfr_recombine_dev_noalloc": ([C.POINTER(u64), C.c_int, u64, u64, P, P, u64, P], C.c_int),
+        "rfr_recombine_noalloc_scratch_bytes": ([], sz),
         "rfr_expand_workspace_bytes": ([C.c_int], sz),
         "rfr_expand_dev": ([C.POINTER(u64), C.c_int, C.c_int, P, sz, P, P], C.c_int),
         "rfr_profile": ([P, C.c_int], C.c_int),
@@ -368,6 +370,29 @@ def recombine_dev(w: Sequence[int], t_lo: int, t_hi: int, cap: int = 4096, strea
     if not sync:
         return cand, count, workspace
     torch.cuda.synchronize()
+    cnt = int(count.cpu().numpy().view(np.uint64)[0])
+    if cnt == (1 << 64) - 1:
+        raise RFRError(-6, "candidate capacity exceeded")
+    arr = cand[: 2 * cnt].cpu().numpy().view(np.uint64).reshape(-1, 2)
+    na = (n - 1 + 1) // 2
+    return sorted(int(a) | (int(b) << na) for a, b in arr)
+
+
+def recombine_dev_noalloc(w: Sequence[int], t_lo: int, t_hi: int, cand, count, stream=None):
+    """The search through the allocation-free entry point: `cand` (2*cap int64)
+    and `count` (one int64) are caller-owned device tensors; the call only
+    enqueues work on `stream` (read `count` after synchronising)."""
+    n = len(w)
+    cap = cand.numel() // 2
+    wv = (C.c_uint64 * n)(*[int(x) & ((1 << 64) - 1) for x in w])
+    _check(lib().rfr_recombine_dev_noalloc(wv, n, t_lo, t_hi, _stream_ptr(stream), C.c_void_p(cand.data_ptr()),
+                                           cap, C.c_void_p(count.data_ptr())))
+
+
+def read_patterns(n: int, cand, count):
+    """Patterns of a finished search (cand/count as filled by the device
+    entry points), sorted; raises RFRError(RFR_ECANDIDATES) on overflow."""
+    import numpy as np
     cnt = int(count.cpu().numpy().view(np.uint64)[0])
     if cnt == (1 << 64) - 1:
         raise RFRError(-6, "candidate capacity exceeded")

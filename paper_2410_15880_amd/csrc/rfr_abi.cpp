@@ -396,6 +396,17 @@ rfr_status rfr_recombine_dev(const uint64_t *w_host, int n, uint64_t t_lo, uint6
     return RFR_OK;
 }
 
+rfr_status rfr_recombine_dev_noalloc(const uint64_t *w_host, int n, uint64_t t_lo, uint64_t t_hi, void *hip_stream,
+                                     uint64_t *cand_dev, uint64_t cap, uint64_t *count_dev) {
+    std::string err;
+    rfr_status st = enqueue_recombine_noalloc(w_host, n, t_lo, t_hi, (hipStream_t)hip_stream, cand_dev, cap,
+                                              count_dev, err);
+    if (st != RFR_OK) return fail(st, err);
+    return RFR_OK;
+}
+
+size_t rfr_recombine_noalloc_scratch_bytes(void) { return rfr::NOALLOC_WS_BYTES; }
+
 size_t rfr_expand_workspace_bytes(int m) { return expand_workspace(m); }
 
 rfr_status rfr_expand_dev(const uint64_t *w_host, int m, int negate, void *workspace, size_t ws_bytes,

@@ -172,6 +172,14 @@ size_t expand_workspace(int m);
 rfr_status enqueue_recombine(const uint64_t *w, int n, uint64_t t_lo, uint64_t t_hi, void *ws,
                              size_t ws_bytes, hipStream_t st, uint64_t *cand, uint64_t cap,
                              uint64_t *count, StageEvents *ev, std::string &err);
+// Allocation-free search: the workspace is a fixed device array of
+// NOALLOC_WS_BYTES per GPU (searches of up to NOALLOC_MAX_N elements fit it,
+// the larger ones streaming half A in chunks).
+constexpr size_t NOALLOC_WS_BYTES = 64ull << 20;
+constexpr int NOALLOC_MAX_N = 46;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+rfr_status enqueue_recombine_noalloc(const uint64_t *w, int n, uint64_t t_lo, uint64_t t_hi, hipStream_t st,
+                                     uint64_t *cand, uint64_t cap, uint64_t *count, std::string &err);
 rfr_status enqueue_expand(const uint64_t *w, int m, int negate, void *ws, size_t ws_bytes,
                           hipStream_t st, uint64_t *sorted, std::string &err);
 

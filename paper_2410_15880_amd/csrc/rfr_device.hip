@@ -32,6 +32,8 @@
 #include <cstdint>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
+#include <string>
 
 #include "rfr_device.h"
 
@@ -1591,7 +1593,7 @@ rfr_status enqueue_recombine(const uint64_t *w, int n, uint64_t t_lo, uint64_t t
     const int ma = na - c;  // weights of half A enumerated per chunk
     JobPlan P;
     plan_job(ma, nb, P, KCAP_MAX);
-    std::vector<uint64_t> wneg(nb);
+    uint64_t wneg[MAX_HALF];  // on the stack: the allocation-free entry point shares this path
     for (int i = 0; i < nb; ++i) wneg[i] = 0 - w[na + i];
     uint32_t grids[NSTAGES];
     stage_blocks(P, grids);
@@ -1600,7 +1602,7 @@ rfr_status enqueue_recombine(const uint64_t *w, int n, uint64_t t_lo, uint64_t t
     const uint64_t nchunks = 1ull << c;
     for (uint64_t t = 0; t < nchunks; ++t) {
         JobArgs J;
-        build_job(P, (char *)ws, w, wneg.data(), t_lo, t_hi, cand, count, cap, J);
+        build_job(P, (char *)ws, w, wneg, t_lo, t_hi, cand, count, cap, J);
         J.kcap = std::min<uint64_t>(cap + 1, KCAP_MAX);
         uint64_t kb = 0;
         for (int i = 0; i < c; ++i)
@@ -1617,6 +1619,49 @@ rfr_status enqueue_recombine(const uint64_t *w, int n, uint64_t t_lo, uint64_t t
         }
     }
     return RFR_OK;
+}
+
+// ---------------------------------------------------------------- allocation-free search
+// Workspace of rfr_recombine_dev_noalloc: one fixed device array per GPU,
+// allocated with the code object when the library is first used on that GPU
+// and held until the process ends.  Host code never passes `scratch` itself to
+// a kernel (on the host it is only a stand-in for the symbol): the device
+// address comes from hipGetSymbolAddress, once per device, with that device
+// current, and is kept in g_scratch_dev.
+static __device__ __align__(256) uint64_t scratch[NOALLOC_WS_BYTES / 8];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[NOALLOC_MAX_DEVICES];
+
+rfr_status enqueue_recombine_noalloc(const uint64_t *w, int n, uint64_t t_lo, uint64_t t_hi, hipStream_t st,
+                                     uint64_t *cand, uint64_t cap, uint64_t *count, std::string &err) {
+    if (n < 2 || n > NOALLOC_MAX_N) {
+        err = "rfr_recombine_dev_noalloc: need 2 <= n <= " + std::to_string(NOALLOC_MAX_N) +
+              " (the fixed device scratch holds " + std::to_string(NOALLOC_WS_BYTES >> 20) + " MiB)";
+        return n < 2 ? RFR_EINVAL : RFR_ENOMEM;
+    }
+    int device = -1;
+    if (hipGetDevice(&device) != hipSuccess || device < 0 || device >= NOALLOC_MAX_DEVICES) {
+        err = "rfr_recombine_dev_noalloc: no usable current device";
+        return RFR_EDEVICE;
+    }
+    void *ws;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_dev[device]) {
+            void *p = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p) {
+                err = std::string("rfr_recombine_dev_noalloc: hipGetSymbolAddress failed: ") + hipGetErrorString(e);
+                return RFR_EDEVICE;
+            }
+            g_scratch_dev[device] = p;
+        }
+        ws = g_scratch_dev[device];
+    }
+    // every counter the pipeline reads is cleared by its first kernel (k_init),
+    // so the previous call's contents need no clearing here
+    return enqueue_recombine(w, n, t_lo, t_hi, ws, NOALLOC_WS_BYTES, st, cand, cap, count, nullptr, err);
 }
 
 size_t recombine_workspace(int n) {
