@@ -22,6 +22,10 @@ What it computes (paper sections in brackets):
 * ``search_hs``      Algorithm C (Section 3.3): EXPAND both halves, sort, and
                      find every pair whose sum lies in the window (FIND that
                      reports all pairs).
+* ``second_trace``   the second power sum of a candidate's monic-transform
+                     roots (Section 2: every power sum of a true factor is an
+                     integer), as weights and a window like the first; the
+                     candidates failing it are dropped before confirmation.
 * ``confirm``        FACTOR's test that the candidate q lies in Z[x]
                      (Section 2, Algorithm FACTOR), done by rounding
                      a_d * q and exact trial division.
@@ -441,6 +445,58 @@ def search(w: Sequence[int], t_lo: int, t_hi: int, brute_max: int = 22) -> List[
 
 
 # --------------------------------------------------------------------------
+# second trace (Section 2: a factor q of the monic transform has integer power
+# sums of its roots; the search tests the first, here the second)
+# --------------------------------------------------------------------------
+
+def second_trace(prim: Sequence[int], groups, deltas, safety: int = 4):
+    """Per-element weights of the second trace and their window.
+
+    Element i contributes e_i = (a_d u)**2 for a real root u and
+    (a_d z)**2 + (a_d conj z)**2 = 2 Re((a_d z)**2) for a pair z; its weight is
+    floor(frac(e_i) * 2**64), computed exactly from the binary value of e_i.
+    The window has the first trace's form [-(n + E2), +E2] with E2 bounding
+    2**64 times the sum of |e_i - e_i(true)| <= |a_d| r (2 |a_d root| + |a_d| r)
+    (twice that for a pair), r the root's inclusion radius.
+    """
+    a_d = int(prim[-1])
+    n = len(groups)
+    vs = []
+    with mpmath.workprec(PREC_BITS):
+        err = mpmath.mpf(0)
+        for (kind, z), dl in zip(groups, deltas):
+            if kind == "r":
+                x = a_d * z
+                e = x * x
+                r = abs(a_d) * dl
+                err += r * (2 * abs(x) + r)
+            else:
+                x = a_d * z
+                e = 2 * mpmath.re(x * x)
+                r = abs(a_d) * dl / 2          # deltas hold 2r for a pair (the bound on 2 Re z)
+                err += 2 * r * (2 * abs(x) + r)
+            vs.append(weight_of(1, e))
+        E2 = int(mpmath.ceil(err * safety * MOD)) + 1
+    return vs, (n + E2, E2)
+
+
+def second_trace_filter(cands: Sequence[int], v: Sequence[int], t2: Tuple[int, int]) -> List[int]:
+    """The candidates whose second trace lies in its window (sums mod 2**64)."""
+    if not cands:
+        return []
+    nbits = max(int(c).bit_length() for c in cands)
+    if nbits <= 64:
+        cs = np.array([int(c) for c in cands], dtype=np.uint64)
+        tot = np.zeros(len(cs), dtype=np.uint64)
+        for i in range(nbits):
+            m = ((cs >> np.uint64(i)) & np.uint64(1)).astype(bool)
+            tot[m] += np.uint64(v[i])
+        keep = _accept_mask(tot, t2[0], t2[1])
+        return [int(c) for c, k in zip(cands, keep) if k]
+    return [c for c in cands if in_window(sum(v[i] for i in range(nbits) if (c >> i) & 1), t2[0], t2[1])]
+
+
+# --------------------------------------------------------------------------
 # confirmation (Algorithm FACTOR, the test q in Z[x]) and atoms
 # --------------------------------------------------------------------------
 
@@ -612,6 +668,9 @@ class Trace:
         self.candidates: List[int] = []
         self.confirmed: Dict[int, List[int]] = {}
         self.groups = []
+        self.tr2_kept: List[int] = []    # candidates whose second trace is an integer
+        self.v2: List[int] = []
+        self.t2 = (0, 0)
 
 
 def factor(coeffs: Sequence[int], trace: Optional[Trace] = None,
@@ -635,9 +694,13 @@ def factor(coeffs: Sequence[int], trace: Optional[Trace] = None,
     w = weights(prim, ts)
     t_lo, t_hi = window(prim, deltas)
     cands = search(w, t_lo, t_hi, brute_max=brute_max)
+    # a true factor's second trace is an integer as well: only those
+    # candidates go on to the (expensive) reconstruction and division
+    v2, t2 = second_trace(prim, groups, deltas)
+    kept = second_trace_filter(cands, v2, t2)
     confirmed: Dict[int, List[int]] = {}
     full = (1 << n) - 1
-    for s in cands:
+    for s in kept:
         r = confirm(prim, groups, s, n)
         if r is not None:
             f, g = r
@@ -654,4 +717,5 @@ def factor(coeffs: Sequence[int], trace: Optional[Trace] = None,
     if trace is not None:
         trace.n, trace.w, trace.t_lo, trace.t_hi = n, w, t_lo, t_hi
         trace.candidates, trace.confirmed, trace.groups = cands, confirmed, groups
+        trace.tr2_kept, trace.v2, trace.t2 = kept, v2, t2
     return cont, canonical(facs + [list(f) for f in extra])

@@ -1,6 +1,6 @@
 """Write expected factorisations for the seeded workloads using the oracle only.
 
-Usage:  python tests/golden/make_golden.py [large|mid|batch|stream] ...
+Usage:  python tests/golden/make_golden.py [large|mid|batch|stream|flood] ...
 
 Each output file maps the workload seed to the oracle's (content, factors) for
 that seeded input; nothing here touches the HIP library.
@@ -27,6 +27,18 @@ def _one(args):
                   "oracle_s": round(time.time() - t0, 2)}
 
 
+def _one_traced(args):
+    """As _one, for a square-free input, with the oracle's candidate counts:
+    patterns whose first trace is in the window, and those whose second is too."""
+    seed, coeffs = args
+    t0 = time.time()
+    tr = R.Trace()
+    cont, facs = R.factor(coeffs, tr)
+    return seed, {"coeffs": coeffs, "content": cont, "factors": [list(f) for f in facs],
+                  "n": tr.n, "tr1_candidates": len(tr.candidates), "tr2_candidates": len(tr.tr2_kept),
+                  "oracle_s": round(time.time() - t0, 2)}
+
+
 def build(name):
     if name == "large":
         ws, procs = W.config_large(), 3
@@ -41,11 +53,13 @@ def build(name):
         ws = [r.work for r in W.config_stream(48, rate_per_s=400.0)] + W.config_repeated(6)
         ws.sort(key=lambda w: -w.degree)
         procs = 3
+    elif name == "flood":
+        ws, procs = W.config_flood(), 2
     else:
         raise SystemExit("unknown set " + name)
     jobs = [(w.seed, w.coeffs) for w in ws]
     with mp.Pool(procs) as pool:
-        res = dict(pool.map(_one, jobs, chunksize=1))
+        res = dict(pool.map(_one_traced if name == "flood" else _one, jobs, chunksize=1))
     out = {"_source": "oracle/rfr_ref.py factor_general() on workloads.config_%s" % name,
            "cases": {str(k): res[k] for k in sorted(res)}}
     path = os.path.join(HERE, "golden_%s.json" % name)

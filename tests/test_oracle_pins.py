@@ -385,3 +385,88 @@ def test_golden_files_match_sympy_factor_list(name):
     for seed, e in g.items():
         want = sympy_factor(e["coeffs"])
         assert (e["content"], [tuple(f) for f in e["factors"]]) == want, seed
+
+
+# ---------------------------------------------------------------- second trace (Section 2, Eq 5-7)
+
+
+def _sd_sign_vectors(k, groups):
+    """Each element's root written as sum_j s_j sqrt(p_j) (Swinnerton-Dyer f_k):
+    the sign vector s in {-1, +1}^k matched by value.  Exact algebra then fixes
+    which subsets have integer power sums: sum over the subset of s_j must
+    vanish for every j (first trace), and of s_j s_l for every j < l (second
+    trace), the square roots of distinct primes and of their distinct products
+    being linearly independent over Q."""
+    import itertools
+    ps = [math.sqrt(sympy.prime(i)) for i in range(1, k + 1)]
+    combos = {}
+    for signs in itertools.product((-1, 1), repeat=k):
+        combos[signs] = sum(s * p for s, p in zip(signs, ps))
+    S = []
+    for kind, z in groups:
+        assert kind == "r"
+        v = float(z)
+        best = min(combos, key=lambda c: abs(combos[c] - v))
+        assert abs(combos[best] - v) < 1e-9
+        S.append(best)
+    return np.array(S, dtype=np.int64)
+
+
+def _exact_trace_masks(S, pats, nbits):
+    bits = ((pats[:, None] >> np.arange(nbits, dtype=np.int64)[None, :]) & 1).astype(np.int64)
+    t1 = bits @ S[:nbits]
+    ok1 = np.all(t1 == 0, axis=1)
+    k = S.shape[1]
+    cross = np.stack([S[:nbits, j] * S[:nbits, l] for j in range(k) for l in range(j + 1, k)], axis=1)
+    ok2 = np.all(bits @ cross == 0, axis=1)
+    return ok1, ok2
+
+
+def test_second_trace_exact_on_f4_brute_force():
+    # every one of the 2^15 patterns of f_4: the oracle's first-trace candidates
+    # are exactly the subsets with an integer root sum, and the ones it keeps
+    # after the second trace exactly those with integer sums of squares too
+    p = W.swinnerton_dyer(4)
+    tr = R.Trace()
+    R.factor(p, tr)
+    n1 = tr.n - 1
+    S = _sd_sign_vectors(4, tr.groups)
+    pats = np.arange(1, 1 << n1, dtype=np.int64)
+    ok1, ok2 = _exact_trace_masks(S, pats, n1)
+    assert sorted(tr.candidates) == [int(x) for x in pats[ok1]]
+    assert sorted(tr.tr2_kept) == [int(x) for x in pats[ok1 & ok2]]
+    assert 0 < len(tr.tr2_kept) < len(tr.candidates)
+
+
+def test_second_trace_filter_on_f5_flood():
+    # f_5: 1.57M patterns with an integer root sum; the second-trace filter
+    # keeps exactly those whose sum of squares is an integer as well
+    p = W.swinnerton_dyer(5)
+    tr = R.Trace()
+    cont, facs = R.factor(p, tr)
+    assert facs == [tuple(p)]
+    S = _sd_sign_vectors(5, tr.groups)
+    pats = np.array(sorted(tr.candidates), dtype=np.int64)
+    ok1, ok2 = _exact_trace_masks(S, pats, tr.n - 1)
+    assert ok1.all()
+    assert sorted(tr.tr2_kept) == [int(x) for x in pats[ok2]]
+    assert len(tr.candidates) == 1570030 and len(tr.tr2_kept) == 528
+
+
+def test_flood_goldens_are_the_known_factorisations():
+    # golden_flood.json (oracle only, make_golden.py) against facts fixed by
+    # construction: f_5 is a minimal polynomial (irreducible), x^32 - x - 1 is
+    # irreducible (Selmer), and the product reconstructs exactly
+    g = json.load(open(os.path.join(HERE, "golden", "golden_flood.json")))["cases"]
+    f5 = W.swinnerton_dyer(5)
+    selmer = [-1, -1] + [0] * 30 + [1]
+    assert sympy.Poly(list(reversed(selmer)), X).is_irreducible
+    ws = W.config_flood()
+    want = {9201: (1, R.canonical([f5])), 9202: (1, R.canonical([f5, selmer]))}
+    for w in ws:
+        e = g[str(w.seed)]
+        assert e["coeffs"] == w.coeffs
+        got = (e["content"], [tuple(f) for f in e["factors"]])
+        assert got == want[w.seed]
+        assert reconstruct(*got) == w.coeffs
+        assert e["tr2_candidates"] < e["tr1_candidates"]

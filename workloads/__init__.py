@@ -32,6 +32,7 @@ import numpy as np
 __all__ = [
     "Workload", "rand_poly", "poly_mul", "planted_split",
     "config_small", "config_mid", "config_large", "config_batch", "config_stream",
+    "config_repeated", "swinnerton_dyer", "config_flood",
 ]
 
 
@@ -208,3 +209,29 @@ def config_repeated(count: int = 24, base_seed: int = 6000, lo: int = -20, hi: i
             planted.append([0, 1])
         out.append(Workload(p, seed, "repeated", planted))
     return out
+
+
+def swinnerton_dyer(k: int) -> List[int]:
+    """Swinnerton-Dyer f_k (Section 2, Eq 5): the minimal polynomial of
+    sqrt(2) + sqrt(3) + ... + sqrt(p_k) (degree 2**k, all roots real), built
+    exactly with sympy."""
+    import sympy
+    x = sympy.Symbol("x")
+    s = sum(sympy.sqrt(sympy.prime(i)) for i in range(1, k + 1))
+    mp = sympy.Poly(sympy.minimal_polynomial(s, x), x)
+    return [int(v) for v in reversed(mp.all_coeffs())]
+
+
+def config_flood() -> List[Workload]:
+    """Inputs that flood the first-trace search with candidates (Section 2,
+    Eq 5-7: subsets of a Swinnerton-Dyer polynomial's roots with an integer
+    sum that are not factors):
+
+    * f_5 (degree 32, 32 real roots), irreducible;
+    * f_5(x) * (x**32 - x - 1) (degree 64), two irreducible factors (the
+      second by Selmer's theorem on x**n - x - 1), coefficients within int64.
+    """
+    f5 = swinnerton_dyer(5)
+    selmer = [-1, -1] + [0] * 30 + [1]
+    return [Workload(f5, 9201, "swinnerton-dyer", [f5]),
+            Workload(poly_mul(f5, selmer), 9202, "planted", [f5, selmer])]
