@@ -76,7 +76,12 @@ typedef struct rfr_result {
     int32_t nfactors;
     int32_t n_elements;        /* n = r + c (Section 2) */
     int32_t n_real;            /* r: real roots */
-    int32_t pad_;
+    int32_t trace_folded;      /* 1 if the search of the first trace overflowed the
+                                  candidate capacity and was redone with the second
+                                  trace folded into the weights (Section 2: the sum of
+                                  squares of a factor's monic-transform roots is an
+                                  integer too), which rejects inside the search every
+                                  pattern whose second trace is not an integer */
     const int32_t *degrees;    /* [nfactors] */
     const int64_t *coeffs;     /* [sum(degrees[k]+1)] */
     uint64_t n_candidates;     /* candidate patterns the search returned */
@@ -99,6 +104,13 @@ rfr_status rfr_create(int device, size_t mem_budget_bytes, rfr_ctx **out);
 
 /* Release a context and all device memory it holds (NULL is ignored). */
 void rfr_destroy(rfr_ctx *ctx);
+
+/* Search design of the plain and served paths: 0 (default) per size class as
+ * the tuning table says (rfr_autotune times both), 1 always the Horowitz-Sahni
+ * pipeline (Section 3.3, Algorithm C), 2 the query design (Section 3.5,
+ * Algorithm E) wherever it applies (halves of at most 2^26 keys).  Results
+ * are the same; only speed and workspace change.  Batches use Algorithm C. */
+rfr_status rfr_set_design(rfr_ctx *ctx, int design);
 
 /* Capacity of candidate patterns per polynomial (default 65536). */
 rfr_status rfr_set_candidate_cap(rfr_ctx *ctx, uint64_t cap);
@@ -253,7 +265,8 @@ rfr_status rfr_prepare_batch(rfr_ctx *ctx, int count, const int64_t *coeffs, con
 
 /* ------------------------------------------------------------------ kernel level */
 
-/* Device workspace for rfr_recombine_dev to search n elements in one pass. */
+/* Device workspace for rfr_recombine_dev to search n elements in one pass
+ * (for n = 70, whose half A is always streamed: in two chunks). */
 size_t rfr_recombine_workspace_bytes(int n);
 
 /* Smallest workspace rfr_recombine_dev accepts for n elements.  Between this
@@ -278,7 +291,8 @@ size_t rfr_recombine_min_workspace_bytes(int n);
  *   count_dev  device uint64: number of patterns found; UINT64_MAX if the
  *              candidate capacity overflowed (then cand_dev is partial)
  * The call only enqueues work; read count_dev after synchronising the stream.
- * Requires 2 <= n <= 2 * 34 + 1 and t_lo + t_hi < 2^32; else RFR_EINVAL. */
+ * Requires 2 <= n <= 70 (from n = 70 on half A, 35 weights, is always
+ * streamed) and t_lo + t_hi < 2^32; else RFR_EINVAL. */
 rfr_status rfr_recombine_dev(const uint64_t *w_host, int n, uint64_t t_lo, uint64_t t_hi,
                              void *workspace, size_t ws_bytes, void *hip_stream,
                              uint64_t *cand_dev, uint64_t cap, uint64_t *count_dev);
@@ -304,6 +318,27 @@ rfr_status rfr_recombine_dev_noalloc(const uint64_t *w_host, int n, uint64_t t_l
 
 /* Size of the fixed device scratch of rfr_recombine_dev_noalloc. */
 size_t rfr_recombine_noalloc_scratch_bytes(void);
+
+/* Device workspace for rfr_recombine_e_dev over n elements (0 if n is out of
+ * its range, 3 <= n <= 53). */
+size_t rfr_recombine_e_workspace_bytes(int n);
+
+/*
+ * The same search by the paper's Algorithm E (Section 3.5: SPLAT, QUERY,
+ * RECOMBINE_E; Section 4: the table stays on the device, only candidates
+ * leave it): half B' (elements [n_a, n-1), negated) is expanded and sorted,
+ * then laid out as the splat table (2 N_B cells, each value at or after its
+ * estimated index, in ascending order); half A (elements [0, n_a)) is never
+ * stored: each of its 2^n_a sums is generated and queried for every table
+ * value inside the window.  Same arguments, outputs and window rules as
+ * rfr_recombine_dev; ws_bytes >= rfr_recombine_e_workspace_bytes(n), about
+ * 41 bytes per B' sum.  *count_dev = UINT64_MAX - 1 (not a valid count) when
+ * B''s sums were too clustered for the expansion's sort: the search did not
+ * run; use rfr_recombine_dev.  The call only enqueues work.
+ */
+rfr_status rfr_recombine_e_dev(const uint64_t *w_host, int n, uint64_t t_lo, uint64_t t_hi,
+                               void *workspace, size_t ws_bytes, void *hip_stream,
+                               uint64_t *cand_dev, uint64_t cap, uint64_t *count_dev);
 
 /* Device workspace needed by rfr_expand_dev for m weights. */
 size_t rfr_expand_workspace_bytes(int m);

@@ -33,6 +33,7 @@ EXPORTS = [
     "rfr_profile", "rfr_profile_read", "rfr_recombine_min_workspace_bytes",
     "rfr_autotune", "rfr_load_tuning", "rfr_prepare_batch", "rfr_results_pack", "rfr_results_free",
     "rfr_squarefree", "rfr_recombine_dev_noalloc", "rfr_recombine_noalloc_scratch_bytes",
+    "rfr_recombine_e_workspace_bytes", "rfr_recombine_e_dev", "rfr_set_design",
 ]
 
 
@@ -54,7 +55,7 @@ STAGES = ["count", "scan", "enum_partition", "tile_sort", "sort_join", "recover"
 class Result(C.Structure):
     _fields_ = [
         ("content", C.c_int64), ("nfactors", C.c_int32), ("n_elements", C.c_int32),
-        ("n_real", C.c_int32), ("pad_", C.c_int32),
+        ("n_real", C.c_int32), ("trace_folded", C.c_int32),
         ("degrees", C.POINTER(C.c_int32)), ("coeffs", C.POINTER(C.c_int64)),
         ("n_candidates", C.c_uint64), ("n_confirmed", C.c_uint64),
         ("t_lo", C.c_uint64), ("t_hi", C.c_uint64),
@@ -80,6 +81,7 @@ def lib():
         "rfr_create": ([C.c_int, sz, C.POINTER(P)], C.c_int),
         "rfr_destroy": ([P], None),
         "rfr_set_candidate_cap": ([P, u64], C.c_int),
+        "rfr_set_design": ([P, C.c_int], C.c_int),
         "rfr_factor": ([P, C.POINTER(i64), C.c_int, C.POINTER(RP)], C.c_int),
         "rfr_factor_batch": ([P, C.c_int, C.POINTER(i64), C.POINTER(i32), C.POINTER(RP), C.POINTER(C.c_int)], C.c_int),
         "rfr_serve_start": ([P, C.c_int, C.c_int], C.c_int),
@@ -100,6 +102,8 @@ def lib():
         "rfr_recombine_dev": ([C.POINTER(u64), C.c_int, u64, u64, P, sz, P, P, u64, P], C.c_int),
         "rfr_recombine_dev_noalloc": ([C.POINTER(u64), C.c_int, u64, u64, P, P, u64, P], C.c_int),
         "rfr_recombine_noalloc_scratch_bytes": ([], sz),
+        "rfr_recombine_e_workspace_bytes": ([C.c_int], sz),
+        "rfr_recombine_e_dev": ([C.POINTER(u64), C.c_int, u64, u64, P, sz, P, P, u64, P], C.c_int),
         "rfr_expand_workspace_bytes": ([C.c_int], sz),
         "rfr_expand_dev": ([C.POINTER(u64), C.c_int, C.c_int, P, sz, P, P], C.c_int),
         "rfr_profile": ([P, C.c_int], C.c_int),
@@ -143,6 +147,7 @@ def _unpack(rp) -> dict:
         k += d + 1
     out = {"content": int(r.content), "factors": facs, "n": int(r.n_elements), "r": int(r.n_real),
            "n_candidates": int(r.n_candidates), "n_confirmed": int(r.n_confirmed),
+           "trace_folded": int(r.trace_folded),
            "t_lo": int(r.t_lo), "t_hi": int(r.t_hi), "ms_roots": r.ms_roots,
            "ms_search": r.ms_search, "ms_confirm": r.ms_confirm}
     lib().rfr_result_free(rp)
@@ -302,6 +307,11 @@ class Context:
         """Time every radix split per size class on this device; install the best."""
         _check(lib().rfr_autotune(self._h, lg_lo, lg_hi, path.encode() if path else None))
 
+    def set_design(self, design: int):
+        """Search design of the plain and served paths: 0 per size class (tuning
+        table), 1 Horowitz-Sahni (Algorithm C), 2 the query design (Algorithm E)."""
+        _check(lib().rfr_set_design(self._h, design))
+
     # ---- profiling
     def profile(self, enable: bool = True):
         _check(lib().rfr_profile(self._h, 1 if enable else 0))
@@ -387,6 +397,29 @@ def recombine_dev_noalloc(w: Sequence[int], t_lo: int, t_hi: int, cand, count, s
     wv = (C.c_uint64 * n)(*[int(x) & ((1 << 64) - 1) for x in w])
     _check(lib().rfr_recombine_dev_noalloc(wv, n, t_lo, t_hi, _stream_ptr(stream), C.c_void_p(cand.data_ptr()),
                                            cap, C.c_void_p(count.data_ptr())))
+
+
+def recombine_e_dev(w: Sequence[int], t_lo: int, t_hi: int, cap: int = 4096, stream=None):
+    """The search by the query design (Algorithm E variant) over torch buffers:
+    the sorted list of patterns, RFRError(RFR_ECANDIDATES) on overflow, or
+    None when B''s sums were too clustered for the design (use recombine_dev)."""
+    import numpy as np
+    import torch
+    n = len(w)
+    L = lib()
+    ws_bytes = L.rfr_recombine_e_workspace_bytes(n)
+    if ws_bytes == 0:
+        raise RFRError(-1, "n out of range for the query design")
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    cand = torch.empty(2 * cap, dtype=torch.int64, device="cuda")
+    count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    wv = (C.c_uint64 * n)(*[int(x) & ((1 << 64) - 1) for x in w])
+    _check(L.rfr_recombine_e_dev(wv, n, t_lo, t_hi, C.c_void_p(ws.data_ptr()), ws_bytes, _stream_ptr(stream),
+                                 C.c_void_p(cand.data_ptr()), cap, C.c_void_p(count.data_ptr())))
+    torch.cuda.synchronize()
+    if int(count.cpu().numpy().view(np.uint64)[0]) == (1 << 64) - 2:
+        return None
+    return read_patterns(n, cand, count)
 
 
 def read_patterns(n: int, cand, count):

@@ -42,6 +42,7 @@ rfr_result *pack_result(const Prepared &P, const Factored &F) {
     r->degrees = deg;
     r->coeffs = co;
     r->n_candidates = F.n_candidates;
+    r->trace_folded = F.trace_folded;
     r->n_confirmed = F.n_confirmed;
     r->t_lo = P.t_lo;
     r->t_hi = P.t_hi;
@@ -120,9 +121,13 @@ rfr_status prepare_dev(RootBuf &b, const int64_t *coeffs, int degree, Prepared &
     return prepare_elements(P, err);
 }
 
-rfr_status slot_init(rfr_ctx *ctx, Slot &s) {
-    if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess)
+rfr_status slot_init(rfr_ctx *ctx, Slot &s, hipStream_t lane) {
+    if (lane) {
+        s.stream = lane;
+        s.own_stream = false;
+    } else if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess) {
         return fail(RFR_EDEVICE, "hipStreamCreate failed");
+    }
     if (rootbuf_init(s.roots, s.stream) != RFR_OK) return RFR_ENOMEM;
     if (hipMalloc(&s.cand_dev, 2 * ctx->cap * sizeof(uint64_t) + 256) != hipSuccess)
         return fail(RFR_ENOMEM, "hipMalloc of the candidate buffer failed");
@@ -141,7 +146,7 @@ void slot_free(rfr_ctx *ctx, Slot &s) {
     if (s.cand_dev) (void)hipFree(s.cand_dev);
     if (s.host) (void)hipHostFree(s.host);
     rootbuf_free(s.roots);
-    if (s.stream) (void)hipStreamDestroy(s.stream);
+    if (s.stream && s.own_stream) (void)hipStreamDestroy(s.stream);
     s = Slot();
 }
 
@@ -162,10 +167,11 @@ size_t choose_workspace(int n, size_t avail) {
     return 0;
 }
 
-rfr_status search_on_slot(rfr_ctx *ctx, Slot &s, const Prepared &P, std::vector<Pat> &cands) {
+rfr_status search_on_slot(rfr_ctx *ctx, Slot &s, const Prepared &P, std::vector<Pat> &cands, int *folded) {
     cands.clear();
+    if (folded) *folded = 0;
     if (P.n <= 1) return RFR_OK;
-    if (P.n > 2 * dev::MAX_HALF + 1) return fail(RFR_EOVERFLOW, "too many elements for the search tables");
+    if (P.n > dev::MAX_SEARCH_N) return fail(RFR_EOVERFLOW, "too many elements for the search tables");
     rfr_status st = RFR_OK;
     if (s.ws_bytes < recombine_workspace(P.n) && chunk_bits(P.n, s.ws_bytes) < 0) {
         // grow within the budget; a search larger than the budget streams half A
@@ -177,23 +183,61 @@ rfr_status search_on_slot(rfr_ctx *ctx, Slot &s, const Prepared &P, std::vector<
     }
     std::string err;
     const bool prof = ctx->profiling && !ctx->serving;
-    st = enqueue_recombine(P.w.data(), P.n, P.t_lo, P.t_hi, s.ws, s.ws_bytes, s.stream, s.cand_dev, s.cap,
-                           s.count_dev, prof ? profile_events(ctx, 0) : nullptr, err);
-    if (st != RFR_OK) return fail(st, err);
     uint64_t *hcount = s.host + 2 * s.cap;
-    if (hipMemcpyAsync(hcount, s.count_dev, 8, hipMemcpyDeviceToHost, s.stream) != hipSuccess ||
-        hipStreamSynchronize(s.stream) != hipSuccess)
-        return fail(RFR_EDEVICE, "device search failed");
-    if (prof) profile_collect(ctx, 0, P.n);
+    // the query design (Algorithm E variant) where the tuning table found it
+    // faster for this size class (or the context asks for it), within its range
+    int na, nb;
+    split_halves(P.n, na, nb);
+    const bool e_ok = nb >= 1 && na <= E_MAX_HALF;
+    bool use_e = e_ok && (ctx->design == 2 || (ctx->design == 0 && get_tune(na).design == 1));
+    if (use_e && s.ws_bytes < recombine_e_workspace(P.n)) {
+        const size_t avail = ctx->budget - (ctx->mem_used - s.ws_bytes);
+        if (recombine_e_workspace(P.n) > avail || ensure_workspace(ctx, s, recombine_e_workspace(P.n)) != RFR_OK)
+            use_e = false;
+    }
+    auto run = [&](const uint64_t *w, uint64_t t_lo, uint64_t t_hi) -> rfr_status {
+        if (use_e) {
+            rfr_status r = enqueue_recombine_e(w, P.n, t_lo, t_hi, s.ws, s.ws_bytes, s.stream, s.cand_dev, s.cap,
+                                               s.count_dev, err);
+            if (r != RFR_OK) return fail(r, err);
+            if (hipMemcpyAsync(hcount, s.count_dev, 8, hipMemcpyDeviceToHost, s.stream) != hipSuccess ||
+                hipStreamSynchronize(s.stream) != hipSuccess)
+                return fail(RFR_EDEVICE, "device search failed");
+            if (*hcount != E_FALLBACK) return RFR_OK;
+            // B' sums too clustered for the query design: Horowitz-Sahni
+        }
+        rfr_status r = enqueue_recombine(w, P.n, t_lo, t_hi, s.ws, s.ws_bytes, s.stream, s.cand_dev, s.cap,
+                                         s.count_dev, prof ? profile_events(ctx, 0) : nullptr, err);
+        if (r != RFR_OK) return fail(r, err);
+        if (hipMemcpyAsync(hcount, s.count_dev, 8, hipMemcpyDeviceToHost, s.stream) != hipSuccess ||
+            hipStreamSynchronize(s.stream) != hipSuccess)
+            return fail(RFR_EDEVICE, "device search failed");
+        if (prof) profile_collect(ctx, 0, P.n);
+        return RFR_OK;
+    };
+    st = run(P.w.data(), P.t_lo, P.t_hi);
+    if (st != RFR_OK) return st;
     uint64_t cnt = *hcount;
+    if (cnt == ~0ull && P.tr2_ok && P.t_lo + P.t2_lo + P.t_hi + P.t2_hi < (1ull << 32)) {
+        // A flood of patterns whose first trace is an integer (Swinnerton-Dyer
+        // like inputs).  A true factor's second trace is an integer too, so
+        // search again over w_i + v_i: a true factor's sum lands in the sum of
+        // the two windows, while a pattern whose second trace is not an integer
+        // lands anywhere (the pre-filter of the second trace, applied inside
+        // the search at no extra table traffic).
+        uint64_t u[dev::MAX_SEARCH_N];
+        for (int i = 0; i < P.n; ++i) u[i] = P.w[i] + P.v2[i];
+        st = run(u, P.t_lo + P.t2_lo, P.t_hi + P.t2_hi);
+        if (st != RFR_OK) return st;
+        cnt = *hcount;
+        if (folded) *folded = 1;
+    }
     if (cnt == ~0ull) return fail(RFR_ECANDIDATES, "candidate capacity exceeded");
     if (cnt) {
         if (hipMemcpyAsync(s.host, s.cand_dev, cnt * 16, hipMemcpyDeviceToHost, s.stream) != hipSuccess ||
             hipStreamSynchronize(s.stream) != hipSuccess)
             return fail(RFR_EDEVICE, "candidate copy failed");
     }
-    int na, nb;
-    split_halves(P.n, na, nb);
     cands.resize(cnt);
     for (uint64_t k = 0; k < cnt; ++k) {
         Pat p;
@@ -221,7 +265,7 @@ rfr_status factor_on_slot(rfr_ctx *ctx, Slot &s, const int64_t *coeffs, int degr
     if (P.n <= 1) {
         trivial_factor(P, F);
     } else {
-        st = search_on_slot(ctx, s, P, cands);
+        st = search_on_slot(ctx, s, P, cands, &F.trace_folded);
         if (st != RFR_OK) return st;
     }
     double t2 = now_ms();
@@ -281,6 +325,13 @@ void rfr_destroy(rfr_ctx *ctx) {
         if (e) (void)hipEventDestroy(e);
     slot_free(ctx, ctx->main);
     delete ctx;
+}
+
+rfr_status rfr_set_design(rfr_ctx *ctx, int design) {
+    if (!ctx || design < 0 || design > 2) return fail(RFR_EINVAL, "design must be 0, 1 or 2");
+    if (ctx->serving) return fail(RFR_EBUSY, "cannot change the design while serving");
+    ctx->design = design;
+    return RFR_OK;
 }
 
 rfr_status rfr_set_candidate_cap(rfr_ctx *ctx, uint64_t cap) {
@@ -379,7 +430,7 @@ rfr_status rfr_weights(const int64_t *coeffs, int degree, uint64_t *w_out, int32
 size_t rfr_recombine_workspace_bytes(int n) { return recombine_workspace(n); }
 
 size_t rfr_recombine_min_workspace_bytes(int n) {
-    if (n < 2 || n > 2 * dev::MAX_HALF + 1) return 0;
+    if (n < 2 || n > dev::MAX_SEARCH_N) return 0;
     int na, nb;
     split_halves(n, na, nb);
     JobPlan P;
@@ -406,6 +457,18 @@ rfr_status rfr_recombine_dev_noalloc(const uint64_t *w_host, int n, uint64_t t_l
 }
 
 size_t rfr_recombine_noalloc_scratch_bytes(void) { return rfr::NOALLOC_WS_BYTES; }
+
+size_t rfr_recombine_e_workspace_bytes(int n) { return recombine_e_workspace(n); }
+
+rfr_status rfr_recombine_e_dev(const uint64_t *w_host, int n, uint64_t t_lo, uint64_t t_hi, void *workspace,
+                               size_t ws_bytes, void *hip_stream, uint64_t *cand_dev, uint64_t cap,
+                               uint64_t *count_dev) {
+    std::string err;
+    rfr_status st = enqueue_recombine_e(w_host, n, t_lo, t_hi, workspace, ws_bytes, (hipStream_t)hip_stream,
+                                        cand_dev, cap, count_dev, err);
+    if (st != RFR_OK) return fail(st, err);
+    return RFR_OK;
+}
 
 size_t rfr_expand_workspace_bytes(int m) { return expand_workspace(m); }
 

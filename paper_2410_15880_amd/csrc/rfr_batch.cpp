@@ -326,7 +326,7 @@ extern "C" rfr_status rfr_factor_batch(rfr_ctx *ctx, int count, const int64_t *c
         const int i = order[k];
         while (!ready[i].load(std::memory_order_acquire)) std::this_thread::yield();
         if (st[i] != RFR_OK || P[i].n <= 1) continue;
-        if (P[i].n > 2 * dev::MAX_HALF + 1) {
+        if (P[i].n > dev::MAX_SEARCH_N) {
             st[i] = RFR_EOVERFLOW;
             err[i] = "too many elements for the search tables";
             continue;
@@ -484,6 +484,7 @@ extern "C" rfr_status rfr_factor_batch(rfr_ctx *ctx, int count, const int64_t *c
 
     // ---- 5. candidates of every searched polynomial
     std::vector<std::vector<Pat>> cands(count);
+    std::vector<int> folded(count, 0);
     auto take = [&](int i) -> rfr_status {
         const int k = slot[i];
         const uint64_t *s = sum_h + (size_t)k * SUMMARY;
@@ -492,7 +493,7 @@ extern "C" rfr_status rfr_factor_batch(rfr_ctx *ctx, int count, const int64_t *c
         split_halves(P[i].n, na, nb);
         if (c == ~0ull) {
             // more candidates than a batch slot holds: redo with the full capacity
-            rfr_status r = search_on_slot(ctx, ctx->main, P[i], cands[i]);
+            rfr_status r = search_on_slot(ctx, ctx->main, P[i], cands[i], &folded[i]);
             if (r != RFR_OK) {
                 st[i] = r;
                 err[i] = g_last_error;
@@ -524,6 +525,7 @@ extern "C" rfr_status rfr_factor_batch(rfr_ctx *ctx, int count, const int64_t *c
                 out[i] = nullptr;
                 if (st[i] == RFR_OK) {
                     Factored F;
+                    F.trace_folded = folded[i];
                     if (P[i].n <= 1) trivial_factor(P[i], F);
                     else st[i] = confirm_and_factor(P[i], cands[i], F, err[i]);
                     if (st[i] == RFR_OK) {

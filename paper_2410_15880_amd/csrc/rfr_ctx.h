@@ -32,6 +32,7 @@ struct RootBuf {
 
 struct Slot {
     hipStream_t stream = nullptr;
+    bool own_stream = true;      // false: the stream is a serving lane shared with other slots
     RootBuf roots;
     void *ws = nullptr;
     size_t ws_bytes = 0;
@@ -59,6 +60,7 @@ struct rfr_ctx {
     size_t budget = 0;
     size_t mem_used = 0;         // bytes of search workspaces held
     uint64_t cap = 65536;        // candidate patterns per polynomial
+    int design = 0;              // search design: 0 per size class (tuning table), 1 Horowitz-Sahni, 2 query (E)
     rfr::Slot main;              // slot of the plain path
     // ---- serving
     bool serving = false;
@@ -69,6 +71,8 @@ struct rfr_ctx {
     std::deque<rfr::Request *> queue;
     std::map<uint64_t, rfr::Request *> reqs;
     int big_running = 0;         // admitted searches that fill the GPU on their own
+    hipStream_t lane_big = nullptr;    // serving: the stream of the searches that fill the GPU
+    hipStream_t lane_small = nullptr;  // serving: the stream of every other request's device work
     uint64_t next_ticket = 1;
     bool stopping = false;
     // ---- batch
@@ -87,9 +91,13 @@ rfr_status fail(rfr_status st, const std::string &msg);
 double now_ms();
 rfr_result *pack_result(const Prepared &P, const Factored &F);
 rfr_status ensure_workspace(rfr_ctx *ctx, Slot &s, size_t need);
-rfr_status slot_init(rfr_ctx *ctx, Slot &s);
+// A slot with a stream of its own, or on `lane` (not owned) when given.
+rfr_status slot_init(rfr_ctx *ctx, Slot &s, hipStream_t lane = nullptr);
 void slot_free(rfr_ctx *ctx, Slot &s);
-rfr_status search_on_slot(rfr_ctx *ctx, Slot &s, const Prepared &P, std::vector<Pat> &cands);
+// *folded (if given) is set to 1 when the search had to fold the second trace
+// into the weights (a first search overflowed the candidate capacity).
+rfr_status search_on_slot(rfr_ctx *ctx, Slot &s, const Prepared &P, std::vector<Pat> &cands,
+                          int *folded = nullptr);
 size_t choose_workspace(int n, size_t avail);
 void tuning_autoload();
 

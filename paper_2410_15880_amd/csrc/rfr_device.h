@@ -18,7 +18,7 @@ constexpr int NT1 = 256;          // threads per workgroup
 constexpr int KPT1 = 32;          // Gray steps (keys per thread) per LDS tile
 constexpr int T1 = NT1 * KPT1;    // keys per K1 tile (64 KB of LDS)
 constexpr int TILES1 = 8;         // tiles per K0/K1 workgroup
-constexpr int MAXB1_LOG = 11;     // level-1 digit bits (buckets) at most
+constexpr int MAXB1_LOG = 12;     // level-1 digit bits (buckets) at most (12 only for halves of 2^34 keys)
 constexpr int MAXB1 = 1 << MAXB1_LOG;
 // ---- K2: per-bucket tile sort by the level-2 digit
 constexpr int KPT2 = 8;           // keys per K2 thread
@@ -44,7 +44,9 @@ constexpr int MAXT = 256;         // tile rows staged per gather chunk
 constexpr int KCAP_MAX = 4096;    // key pairs held per search
 constexpr int RBITS_LOG = 18;     // LDS bitmap of candidate-key prefixes
 constexpr int RBITS = 1 << RBITS_LOG;
-constexpr int MAX_HALF = 34;      // elements per half (2^34 keys)
+constexpr int MAX_HALF = 34;      // elements per enumerated half (2^34 keys)
+constexpr int MAX_SEARCH_N = 2 * MAX_HALF + 2;  // elements of a search (n - 1 = 69 leaves half A
+                                  // 35 weights: it is then streamed in at least 2 chunks)
 constexpr int MAX_CHUNK_BITS = 8; // half A streamed in at most 2^8 chunks
 constexpr int RECOVER_FEW = 64;   // candidate keys handled by the meet-in-the-middle recovery
 constexpr int SPT4 = 16;          // Gray steps per thread in that recovery
@@ -119,6 +121,7 @@ struct JobPlan {
     HalfPlan h[2];
     int B1 = 0, B2 = 0;
     int t2log = dev::T2_LOG;
+    int sub = dev::SUB_LOG;  // log2 of the mean keys per sub-bucket of the larger half
     uint64_t kcap = dev::KCAP_MAX;
     uint64_t *kp = nullptr, *rec = nullptr, *counters = nullptr;
 };
@@ -150,9 +153,10 @@ struct SmallJob {
 
 // Autotuned digit split for one size class (log2 of the larger half).
 struct Tune {
-    int b1;       // level-1 digit bits (-1: default)
-    int sub_log;  // log2 of the mean keys per sub-bucket (SUB_LOG_MIN..SUB_LOG; -1: default)
-    double ms;    // time measured by the autotuner
+    int b1;          // level-1 digit bits (-1: default)
+    int sub_log;     // log2 of the mean keys per sub-bucket (SUB_LOG_MIN..SUB_LOG; -1: default)
+    double ms;       // time measured by the autotuner
+    int design = 0;  // 1: the query design (Algorithm E variant) was faster for this size class
 };
 void set_tune(int lg, Tune t);
 Tune get_tune(int lg);
@@ -180,6 +184,16 @@ constexpr int NOALLOC_MAX_N = 46;
 constexpr int NOALLOC_MAX_DEVICES = 64;
 rfr_status enqueue_recombine_noalloc(const uint64_t *w, int n, uint64_t t_lo, uint64_t t_hi, hipStream_t st,
                                      uint64_t *cand, uint64_t cap, uint64_t *count, std::string &err);
+// Algorithm E variant (Section 3.5): half B' expanded, sorted and laid out
+// as a splat table; half A generated and queried, never stored.  Halves of at
+// most 2^E_MAX_HALF keys.  A count of E_FALLBACK means the design could not
+// run (B' sums too clustered for the expansion's sort): search with
+// enqueue_recombine instead.
+constexpr int E_MAX_HALF = 26;
+constexpr uint64_t E_FALLBACK = ~0ull - 1;
+size_t recombine_e_workspace(int n);
+rfr_status enqueue_recombine_e(const uint64_t *w, int n, uint64_t t_lo, uint64_t t_hi, void *ws, size_t ws_bytes,
+                               hipStream_t st, uint64_t *cand, uint64_t cap, uint64_t *count, std::string &err);
 rfr_status enqueue_expand(const uint64_t *w, int m, int negate, void *ws, size_t ws_bytes,
                           hipStream_t st, uint64_t *sorted, std::string &err);
 

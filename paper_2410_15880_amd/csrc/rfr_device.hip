@@ -1046,6 +1046,7 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(5))) void k
     const JobArgs *Jp;
     uint32_t s;
     if (!pick<MULTI>(Jarg, M, ST_JOIN, Jp, s)) return;
+    if (!MULTI) s += blockIdx.y * gridDim.x;  // grids of more than 2^22 sub-buckets
     const JobArgs &J = *Jp;
     const int LB = J.B1 + J.B2;
     const uint32_t NS = 1u << LB;
@@ -1288,6 +1289,10 @@ __global__ __launch_bounds__(NT1) void k_pairs(JobArgs Jarg, Multi M) {
         if (threadIdx.x == 0) *J.out_count = ~0ull;
         return;
     }
+    if (*J.flags & 4u) {  // the query design could not run (its B' sort overflowed)
+        if (threadIdx.x == 0) *J.out_count = E_FALLBACK;
+        return;
+    }
     const uint32_t ra = (uint32_t)min(J.rec_count[0], J.kcap), rb = (uint32_t)min(J.rec_count[1], J.kcap);
     for (uint32_t p = threadIdx.x; p < cnt; p += NT1) {
         const uint64_t a = J.kp[2 * p], bk = J.kp[2 * p + 1];
@@ -1341,7 +1346,7 @@ static Tune g_tune[MAX_HALF + 1] = {};
 static bool g_tune_init = false;
 static void tune_defaults() {
     if (g_tune_init) return;
-    for (auto &t : g_tune) t = Tune{-1, -1, 0.0};
+    for (auto &t : g_tune) t = Tune{-1, -1, 0.0, 0};
     g_tune_init = true;
 }
 void set_tune(int lg, Tune t) {
@@ -1350,17 +1355,20 @@ void set_tune(int lg, Tune t) {
 }
 Tune get_tune(int lg) {
     tune_defaults();
-    return (lg >= 0 && lg <= MAX_HALF) ? g_tune[lg] : Tune{-1, -1, 0.0};
+    return (lg >= 0 && lg <= MAX_HALF) ? g_tune[lg] : Tune{-1, -1, 0.0, 0};
 }
 
-static void plan_bits(uint64_t nmax, bool batch, int &B1, int &B2) {
+static void plan_bits(uint64_t nmax, bool batch, bool expand, int &B1, int &B2, int &sub) {
     int lg = 0;
     while ((1ull << lg) < nmax) ++lg;
-    const Tune tn = get_tune(lg);
-    // The table is timed on one search at a time, where smaller sub-buckets
-    // (more workgroups) fill the chip; a batch fills it with its many
-    // searches, so it takes the largest sub-buckets (fewest workgroups).
-    const int sub = batch ? SUB_LOG : (tn.sub_log >= SUB_LOG_MIN && tn.sub_log <= SUB_LOG) ? tn.sub_log : SUB_LOG;
+    const Tune tn = expand ? Tune{-1, -1, 0.0, 0} : get_tune(lg);
+    // The join and EXPAND hold a sub-bucket in LDS (at most CAP3 keys per
+    // half), so the mean is at most 2^SUB_LOG.  The search table is timed on
+    // one search at a time, where smaller sub-buckets (more workgroups) fill
+    // the chip; a batch fills it with its many searches, so it takes the
+    // largest sub-buckets, as EXPAND does.
+    if (expand || batch) sub = SUB_LOG;
+    else sub = (tn.sub_log >= SUB_LOG_MIN && tn.sub_log <= SUB_LOG) ? tn.sub_log : SUB_LOG;
     int LB = lg > sub ? lg - sub : 0;
     if (LB > MAXB1_LOG + MAXB2_LOG) LB = MAXB1_LOG + MAXB2_LOG;
     if (tn.b1 >= 0) {
@@ -1376,7 +1384,9 @@ static void plan_bits(uint64_t nmax, bool batch, int &B1, int &B2) {
         B1 = LB < 8 ? LB : 8;
         B2 = LB - B1;
     } else {
-        B1 = std::min(MAXB1_LOG, (LB + 1) / 2);
+        // level 1 at most 2^11 buckets (runs of 4 keys per K1 tile); the 12th
+        // bit only when level 2 is full (halves of 2^34 keys)
+        B1 = std::min(11, (LB + 1) / 2);
         B2 = LB - B1;
     }
     if (B2 > MAXB2_LOG) {
@@ -1427,7 +1437,7 @@ uint64_t plan_job(int na, int nb, JobPlan &P, uint64_t kcap, bool batch) {
         plan_half(nb, P.h[1]);
         nmax = std::max(nmax, P.h[1].N);
     }
-    plan_bits(nmax, batch, P.B1, P.B2);
+    plan_bits(nmax, batch, nb < 0, P.B1, P.B2, P.sub);
     // One search whose level-1 buckets average four or more 2^13-key tiles
     // takes them: half as many tile segments per sub-bucket for K3 to gather.
     // A batch keeps the smaller tiles (its buckets hold a few partial ones).
@@ -1495,6 +1505,7 @@ static hipError_t launch_all(const JobArgs &J, const Multi &M, const uint32_t *g
     hipLaunchKernelGGL((k_init<MULTI>), dim3(grids[ST_INIT]), dim3(64), 0, st, J, M);
     if (maxB1 <= 8) hipLaunchKernelGGL((k_enum<true, 256, MULTI>), dim3(grids[ST_COUNT], nh), dim3(NT1), 0, st, J, M);
     else if (maxB1 <= 10) hipLaunchKernelGGL((k_enum<true, 1024, MULTI>), dim3(grids[ST_COUNT], nh), dim3(NT1), 0, st, J, M);
+    else if (maxB1 <= 11) hipLaunchKernelGGL((k_enum<true, 2048, MULTI>), dim3(grids[ST_COUNT], nh), dim3(NT1), 0, st, J, M);
     else hipLaunchKernelGGL((k_enum<true, MAXB1, MULTI>), dim3(grids[ST_COUNT], nh), dim3(NT1), 0, st, J, M);
     rec(1);
     hipLaunchKernelGGL((k_scan_cols<MULTI>), dim3(grids[ST_COLS], nh), dim3(NT1), 0, st, J, M);
@@ -1502,6 +1513,7 @@ static hipError_t launch_all(const JobArgs &J, const Multi &M, const uint32_t *g
     rec(2);
     if (maxB1 <= 8) hipLaunchKernelGGL((k_enum<false, 256, MULTI>), dim3(grids[ST_ENUM], nh), dim3(NT1), 0, st, J, M);
     else if (maxB1 <= 10) hipLaunchKernelGGL((k_enum<false, 1024, MULTI>), dim3(grids[ST_ENUM], nh), dim3(NT1), 0, st, J, M);
+    else if (maxB1 <= 11) hipLaunchKernelGGL((k_enum<false, 2048, MULTI>), dim3(grids[ST_ENUM], nh), dim3(NT1), 0, st, J, M);
     else hipLaunchKernelGGL((k_enum<false, MAXB1, MULTI>), dim3(grids[ST_ENUM], nh), dim3(NT1), 0, st, J, M);
     rec(3);
     // the workgroup holds the launch's largest tile (a job's tiles may be smaller)
@@ -1521,7 +1533,10 @@ static hipError_t launch_all(const JobArgs &J, const Multi &M, const uint32_t *g
         hipLaunchKernelGGL((k_join<true, MULTI>), dim3(grids[ST_JOIN]), dim3(NT3), 0, st, J, M, sorted);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL((k_join<false, MULTI>), dim3(grids[ST_JOIN]), dim3(NT3), 0, st, J, M, (uint64_t *)nullptr);
+    // a grid's work-items must number below 2^32: beyond 2^22 sub-buckets
+    // (single searches only) the grid takes a second dimension
+    const dim3 gj = (!MULTI && grids[ST_JOIN] > (1u << 22)) ? dim3(1u << 22, grids[ST_JOIN] >> 22) : dim3(grids[ST_JOIN]);
+    hipLaunchKernelGGL((k_join<false, MULTI>), gj, dim3(NT3), 0, st, J, M, (uint64_t *)nullptr);
     rec(5);
     hipLaunchKernelGGL((k_recover_few<MULTI>), dim3(grids[ST_RFEW], 2), dim3(NT1), 0, st, J, M);
     hipLaunchKernelGGL((k_recover<MULTI>), dim3(grids[ST_RMANY], 2), dim3(NT1), 0, st, J, M);
@@ -1536,7 +1551,7 @@ static hipError_t launch_all(const JobArgs &J, const Multi &M, const uint32_t *g
 int chunk_bits(int n, size_t ws_bytes) {
     int na, nb;
     split_halves(n, na, nb);
-    for (int c = 0; c <= std::min(na, MAX_CHUNK_BITS); ++c) {
+    for (int c = std::max(0, na - MAX_HALF); c <= std::min(na, MAX_CHUNK_BITS); ++c) {
         JobPlan P;
         if (plan_job(na - c, nb, P, KCAP_MAX) <= ws_bytes) return c;
     }
@@ -1548,8 +1563,8 @@ __global__ __launch_bounds__(NTS) void k_small_one(SmallJob S);  // below, with 
 rfr_status enqueue_recombine(const uint64_t *w, int n, uint64_t t_lo, uint64_t t_hi, void *ws,
                              size_t ws_bytes, hipStream_t st, uint64_t *cand, uint64_t cap,
                              uint64_t *count, StageEvents *ev, std::string &err) {
-    if (!w || n < 2 || n > 2 * MAX_HALF + 1 || !ws || !cand || !count) {
-        err = "rfr_recombine_dev: bad argument (need 2 <= n <= 69 and non-NULL buffers)";
+    if (!w || n < 2 || n > MAX_SEARCH_N || !ws || !cand || !count) {
+        err = "rfr_recombine_dev: bad argument (need 2 <= n <= 70 and non-NULL buffers)";
         return RFR_EINVAL;
     }
     if (t_lo >= (1ull << 32) || t_hi >= (1ull << 32) || t_lo + t_hi >= (1ull << 32)) {
@@ -1665,11 +1680,12 @@ rfr_status enqueue_recombine_noalloc(const uint64_t *w, int n, uint64_t t_lo, ui
 }
 
 size_t recombine_workspace(int n) {
-    if (n < 2 || n > 2 * MAX_HALF + 1) return 0;
+    if (n < 2 || n > MAX_SEARCH_N) return 0;
     int na, nb;
     split_halves(n, na, nb);
     JobPlan P;
-    return plan_job(na, nb, P, KCAP_MAX);
+    // a half A beyond MAX_HALF weights is always streamed: its largest chunk
+    return plan_job(std::min(na, MAX_HALF), nb, P, KCAP_MAX);
 }
 
 size_t expand_workspace(int m) {
@@ -1914,6 +1930,337 @@ hipError_t launch_small(const SmallJob *jobs_dev, int njobs, uint32_t *queue_dev
     hipLaunchKernelGGL(k_small_init, dim3(1), dim3(64), 0, st, queue_dev);
     hipLaunchKernelGGL(k_small, dim3(grid), dim3(NTS), 0, st, jobs_dev, njobs, queue_dev);
     return hipGetLastError();
+}
+
+// ================================================================= Algorithm E variant
+// Section 3.5 (SPLAT, QUERY, RECOMBINE_E) and Section 4: half B' is expanded
+// and sorted once (the EXPAND kernels above), then laid out as the paper's
+// splat table -- k = 2 N_B cells, value x homed at cell floor(k x / 2^64),
+// every value at or after its home, in ascending order, empty cells between
+// runs -- and half A is never stored or sorted: every A key is generated by
+// the Gray-code walk and looked up in the table (QUERY, reporting every
+// partner in the window instead of the first).  Only candidate key pairs
+// leave the query; the recovery and pair kernels of the search follow.
+//
+// The table is what inserting the sorted values one after another by the
+// paper's INSERT gives: with values in ascending order no exchange happens,
+// and value i lands at p_i = max(home_i, p_(i-1) + 1) = i + max_(j <= i)
+// (home_j - j), a prefix maximum.  Cells are not wrapped around: the table
+// has N_B extra cells at its end for the runs that pass cell k - 1.
+namespace dev {
+
+struct SplatArgs {
+    const uint64_t *sorted;  // [nb] B' keys, ascending
+    uint64_t *tbl;           // [tlen] cell values
+    uint32_t *occ;           // [ceil(tlen / 32)] occupied cells
+    int64_t *bmax;           // [nblk] per-block maxima of home_i - i, then their exclusive prefix maxima
+    uint64_t nb, tlen;
+    int hsh;                 // home(x) = x >> hsh (k = 2^(64 - hsh) cells)
+    int nblk;
+    const uint32_t *xflags;  // the expansion's flags (bit 0: a sub-bucket beyond its sort)
+};
+constexpr int SPT_E = 16;               // values per thread in the table build
+constexpr int SPB_E = NT1 * SPT_E;      // values per block
+
+__global__ __launch_bounds__(NT1) void k_splat_clear(SplatArgs S) {
+    const uint64_t words = (S.tlen + 31) / 32;
+    for (uint64_t i = (uint64_t)blockIdx.x * NT1 + threadIdx.x; i < words; i += (uint64_t)gridDim.x * NT1)
+        S.occ[i] = 0;
+}
+
+__device__ __forceinline__ int64_t max_i64(int64_t a, int64_t b) { return a > b ? a : b; }
+
+template <int NTH>
+__device__ __forceinline__ int64_t block_max_i64(int64_t v, int64_t *s_tmp) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max_i64(v, __shfl_xor(v, o, 64));
+    if (lane == 0) s_tmp[wv] = v;
+    __syncthreads();
+    int64_t r = s_tmp[0];
+    for (int i = 1; i < NTH / 64; ++i) r = max_i64(r, s_tmp[i]);
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(NT1) void k_splat_max(SplatArgs S) {
+    __shared__ int64_t s_tmp[NT1 / 64];
+    const uint64_t i0 = (uint64_t)blockIdx.x * SPB_E;
+    int64_t m = INT64_MIN;
+    for (int k = 0; k < SPT_E; ++k) {
+        const uint64_t i = i0 + (uint64_t)k * NT1 + threadIdx.x;
+        if (i < S.nb) m = max_i64(m, (int64_t)(S.sorted[i] >> S.hsh) - (int64_t)i);
+    }
+    m = block_max_i64<NT1>(m, s_tmp);
+    if (threadIdx.x == 0) S.bmax[blockIdx.x] = m;
+}
+
+// bmax[b] becomes the maximum over blocks before b (INT64_MIN for block 0)
+__global__ __launch_bounds__(NT1) void k_splat_scan(SplatArgs S) {
+    __shared__ int64_t s_tmp[NT1 / 64];
+    int64_t carry = INT64_MIN;
+    for (int base = 0; base < S.nblk; base += NT1) {
+        const int i = base + (int)threadIdx.x;
+        const int64_t v = i < S.nblk ? S.bmax[i] : INT64_MIN;
+        // inclusive prefix maximum across the block
+        int64_t inc = v;
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t t = __shfl_up(inc, o, 64);
+            if (lane >= o) inc = max_i64(inc, t);
+        }
+        if (lane == 63) s_tmp[wv] = inc;
+        __syncthreads();
+        int64_t before = carry;
+        for (int w = 0; w < wv; ++w) before = max_i64(before, s_tmp[w]);
+        int64_t ex = __shfl_up(inc, 1, 64);
+        if (lane == 0) ex = INT64_MIN;
+        const int64_t excl = max_i64(before, ex);
+        int64_t tot = carry;
+        for (int w = 0; w < NT1 / 64; ++w) tot = max_i64(tot, s_tmp[w]);
+        __syncthreads();
+        if (i < S.nblk) S.bmax[i] = excl;
+        carry = tot;
+    }
+}
+
+__global__ __launch_bounds__(NT1) void k_splat_place(SplatArgs S) {
+    __shared__ int64_t s_tmp[NT1 / 64 + 1];
+    const uint64_t i0 = (uint64_t)blockIdx.x * SPB_E + (uint64_t)threadIdx.x * SPT_E;
+    uint64_t x[SPT_E];
+    int64_t run = INT64_MIN;
+#pragma unroll
+    for (int k = 0; k < SPT_E; ++k) {
+        const uint64_t i = i0 + k;
+        x[k] = i < S.nb ? S.sorted[i] : 0;
+        if (i < S.nb) run = max_i64(run, (int64_t)(x[k] >> S.hsh) - (int64_t)i);
+    }
+    // exclusive prefix maximum of the threads' maxima, then the blocks before
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int64_t inc = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t t = __shfl_up(inc, o, 64);
+        if (lane >= o) inc = max_i64(inc, t);
+    }
+    if (lane == 63) s_tmp[wv] = inc;
+    __syncthreads();
+    int64_t m = S.bmax[blockIdx.x];
+    for (int w = 0; w < wv; ++w) m = max_i64(m, s_tmp[w]);
+    int64_t ex = __shfl_up(inc, 1, 64);
+    if (lane != 0) m = max_i64(m, ex);
+#pragma unroll
+    for (int k = 0; k < SPT_E; ++k) {
+        const uint64_t i = i0 + k;
+        if (i >= S.nb) break;
+        m = max_i64(m, (int64_t)(x[k] >> S.hsh) - (int64_t)i);
+        const uint64_t p = i + (uint64_t)m;
+        S.tbl[p] = x[k];
+        atomicOr(&S.occ[p >> 5], 1u << (p & 31));
+    }
+}
+
+// QUERY over [lo, hi] (lo <= hi): from lo's home cell, skip values below lo,
+// report values up to hi, stop at a value above hi or at an empty cell past
+// hi's home (every value <= hi sits in the run that starts at or before it).
+__device__ __forceinline__ void splat_query(const JobArgs &J, const SplatArgs &S, uint64_t a, uint64_t lo,
+                                            uint64_t hi) {
+    const uint64_t e = hi >> S.hsh;
+    for (uint64_t i = lo >> S.hsh; i < S.tlen; ++i) {
+        if ((S.occ[i >> 5] >> (i & 31)) & 1u) {
+            const uint64_t x = S.tbl[i];
+            if (x > hi) break;
+            if (x >= lo) emit_pair(J, a, x);
+        } else if (i >= e) {
+            break;
+        }
+    }
+}
+
+// RECOMBINE_E's loop: the A keys of Gray steps [h0, h1) of this workgroup
+// (lane l owns the low L pattern bits, as in the enumeration kernels), each
+// queried for B' keys b' with b' - a in [-t_hi, t_lo] (mod 2^64).
+__global__ __launch_bounds__(NT1) void k_query(JobArgs J, SplatArgs S) {
+    const HalfArgs &H = J.h[0];
+    const uint32_t wg = blockIdx.x;
+    if (wg >= H.nwg1) return;
+    if (*S.xflags & 1u) {
+        if (wg == 0 && threadIdx.x == 0) atomicOr(J.flags, 4u);
+        return;
+    }
+    const int tid = threadIdx.x;
+    const int nl = 1 << H.L;
+    const bool act = tid < nl;
+    __shared__ uint64_t s_w[64];
+    if (tid < H.m) s_w[tid] = J.wts[0][tid];
+    __syncthreads();
+    uint64_t slo = J.kbase[0];
+    for (int i = 0; i < H.L; ++i)
+        if ((tid >> i) & 1) slo += s_w[i];
+    const uint64_t h0 = (uint64_t)wg * H.spw;
+    const uint64_t h1 = min(h0 + (uint64_t)H.spw, H.steps);
+    uint64_t g = h0 ^ (h0 >> 1);
+    uint64_t shi = 0;
+    for (int i = 0; i < H.m - H.L; ++i)
+        if ((g >> i) & 1) shi += s_w[H.L + i];
+    const uint64_t t_lo = J.t_lo, t_hi = J.t_hi;
+    for (uint64_t h = h0; h < h1; ++h) {
+        if (act) {
+            const uint64_t a = slo + shi;
+            const uint64_t lo = a - t_hi, hi = a + t_lo;
+            if (lo <= hi) {
+                splat_query(J, S, a, lo, hi);
+            } else {  // the window wraps past 0
+                splat_query(J, S, a, lo, ~0ull);
+                splat_query(J, S, a, 0, hi);
+            }
+        }
+        const uint64_t t = h + 1;
+        if (t < h1) {
+            const int bb = __builtin_ctzll(t);
+            g ^= 1ull << bb;
+            const uint64_t wb = s_w[H.L + bb];
+            shi += ((g >> bb) & 1) ? wb : (0 - wb);
+        }
+    }
+}
+
+}  // namespace dev
+
+// Workspace of the query design: the expansion of half B' and its sorted
+// output, the table and its occupancy bits, the per-block maxima, and the
+// candidate buffers of the recovery.
+struct EPlan {
+    JobPlan X;  // expansion of half B'
+    uint64_t off_sorted, off_tbl, off_occ, off_bmax, off_kp, off_rec, off_cnt, total;
+    uint64_t nb, tlen;
+    int hsh, nblk;
+};
+
+static uint64_t e_plan(int na, int nb, EPlan &E) {
+    (void)na;
+    uint64_t off = plan_job(nb, -1, E.X, 1);
+    auto take = [&](uint64_t bytes) {
+        off = align_up(off, 256);
+        const uint64_t o = off;
+        off += bytes;
+        return o;
+    };
+    E.nb = 1ull << nb;
+    E.hsh = 64 - (nb + 1);  // k = 2 N_B cells
+    E.tlen = (2ull << nb) + E.nb;
+    E.nblk = (int)((E.nb + SPB_E - 1) / SPB_E);
+    E.off_sorted = take(E.nb * 8);
+    E.off_tbl = take(E.tlen * 8);
+    E.off_occ = take((E.tlen + 31) / 32 * 4);
+    E.off_bmax = take((uint64_t)E.nblk * 8);
+    E.off_kp = take((uint64_t)KCAP_MAX * 16);
+    E.off_rec = take(2ull * KCAP_MAX * 16);
+    E.off_cnt = take(64);
+    E.total = align_up(off, 256);
+    return E.total;
+}
+
+size_t recombine_e_workspace(int n) {
+    if (n < 2 || n > 2 * E_MAX_HALF + 1) return 0;
+    int na, nb;
+    split_halves(n, na, nb);
+    if (nb < 1) return 0;
+    EPlan E;
+    return e_plan(na, nb, E);
+}
+
+rfr_status enqueue_recombine_e(const uint64_t *w, int n, uint64_t t_lo, uint64_t t_hi, void *ws, size_t ws_bytes,
+                               hipStream_t st, uint64_t *cand, uint64_t cap, uint64_t *count, std::string &err) {
+    if (!w || n < 2 || n > 2 * E_MAX_HALF + 1 || !ws || !cand || !count || cap < 1) {
+        err = "rfr_recombine_e_dev: bad argument (need 2 <= n <= 2 * 26 + 1 and non-NULL buffers)";
+        return RFR_EINVAL;
+    }
+    int na, nb;
+    split_halves(n, na, nb);
+    if (nb < 1) {  // n = 2: no B' weights; the HS pipeline covers it
+        err = "rfr_recombine_e_dev: needs n >= 3";
+        return RFR_EINVAL;
+    }
+    EPlan E;
+    if (e_plan(na, nb, E) > ws_bytes) {
+        err = "rfr_recombine_e_dev: workspace too small";
+        return RFR_ENOMEM;
+    }
+    char *base = (char *)ws;
+    // 1. EXPAND of half B' (negated weights) into the sorted array
+    uint64_t wneg[MAX_HALF];
+    for (int i = 0; i < nb; ++i) wneg[i] = 0 - w[na + i];
+    uint64_t *sorted = (uint64_t *)(base + E.off_sorted);
+    JobArgs JX;
+    build_job(E.X, base, wneg, nullptr, 0, 0, nullptr, nullptr, 0, JX);
+    JX.kcap = 1;
+    uint32_t gx[NSTAGES];
+    stage_blocks(E.X, gx);
+    gx[ST_TILE2] = (gx[ST_TILE2] + 7) & ~7u;
+    Multi M{};
+    if (launch_all<false>(JX, M, gx, 1, E.X.B1, E.X.B2, E.X.t2log, false, sorted, st, nullptr) != hipSuccess) {
+        err = "kernel launch failed";
+        return RFR_EDEVICE;
+    }
+    // 2. the search job: half A enumerated by the query, both halves recovered
+    JobArgs J{};
+    HalfPlan ha, hb;
+    plan_half(na, ha);
+    plan_half(nb, hb);
+    J.h[0] = HalfArgs{};
+    J.h[1] = HalfArgs{};
+    for (int k = 0; k < 2; ++k) {
+        const HalfPlan &h = k ? hb : ha;
+        J.h[k].N = h.N;
+        J.h[k].steps = h.steps;
+        J.h[k].spw = h.spw;
+        J.h[k].nwg1 = h.nwg1;
+        J.h[k].m = h.m;
+        J.h[k].L = h.L;
+    }
+    for (int i = 0; i < na; ++i) J.wts[0][i] = w[i];
+    for (int i = 0; i < nb; ++i) J.wts[1][i] = wneg[i];
+    J.t_lo = t_lo;
+    J.t_hi = t_hi;
+    J.kp = (uint64_t *)(base + E.off_kp);
+    J.rec = (uint64_t *)(base + E.off_rec);
+    uint64_t *ctr = (uint64_t *)(base + E.off_cnt);
+    J.kp_count = ctr;
+    J.flags = (uint32_t *)(ctr + 2);
+    J.rec_count = ctr + 3;
+    J.kcap = std::min<uint64_t>(cap + 1, KCAP_MAX);
+    J.out = cand;
+    J.out_count = count;
+    J.cap = cap;
+    J.first_chunk = 1;
+    SplatArgs S{};
+    S.sorted = sorted;
+    S.tbl = (uint64_t *)(base + E.off_tbl);
+    S.occ = (uint32_t *)(base + E.off_occ);
+    S.bmax = (int64_t *)(base + E.off_bmax);
+    S.nb = E.nb;
+    S.tlen = E.tlen;
+    S.hsh = E.hsh;
+    S.nblk = E.nblk;
+    S.xflags = JX.flags;
+    const uint32_t clear_grid = (uint32_t)std::min<uint64_t>(((E.tlen + 31) / 32 + NT1 - 1) / NT1, 4096);
+    hipLaunchKernelGGL((k_init<false>), dim3(1), dim3(64), 0, st, J, M);
+    hipLaunchKernelGGL(k_splat_clear, dim3(clear_grid), dim3(NT1), 0, st, S);
+    hipLaunchKernelGGL(k_splat_max, dim3(E.nblk), dim3(NT1), 0, st, S);
+    hipLaunchKernelGGL(k_splat_scan, dim3(1), dim3(NT1), 0, st, S);
+    hipLaunchKernelGGL(k_splat_place, dim3(E.nblk), dim3(NT1), 0, st, S);
+    hipLaunchKernelGGL(k_query, dim3(ha.nwg1), dim3(NT1), 0, st, J, S);
+    const uint32_t rfew = (uint32_t)((std::max(ha.steps, hb.steps) + (uint64_t)NT1 * SPT4 - 1) / ((uint64_t)NT1 * SPT4));
+    hipLaunchKernelGGL((k_recover_few<false>), dim3(rfew, 2), dim3(NT1), 0, st, J, M);
+    hipLaunchKernelGGL((k_recover<false>), dim3(std::max(ha.nwg1, hb.nwg1), 2), dim3(NT1), 0, st, J, M);
+    hipLaunchKernelGGL((k_pairs<false>), dim3(1), dim3(NT1), 0, st, J, M);
+    if (hipGetLastError() != hipSuccess) {
+        err = "kernel launch failed";
+        return RFR_EDEVICE;
+    }
+    return RFR_OK;
 }
 
 }  // namespace rfr

@@ -497,6 +497,49 @@ static rfr_status weights_window(Prepared &P, std::string &err) {
     }
     P.t_lo = (uint64_t)P.n + E;
     P.t_hi = E;
+    // Second trace of every element (Section 2: the power sums of a factor's
+    // monic-transform roots are integers).  A real root u gives e = tau^2 with
+    // tau = a_d u; a conjugate pair z gives e = 2 Re(s^2) with s = a_d z.  With
+    // |tau - tau_true| <= |a_d| delta: |e - e_true| <= |a_d| delta (2|tau| +
+    // |a_d| delta), twice that for a pair.  Weights and window follow the
+    // first trace's rules; the search folds them in only when its candidates
+    // overflow (a flood of patterns whose first trace is an integer).
+    P.v2.clear();
+    P.tr2_ok = true;
+    double sum_err2 = 0, sum_e = 0;
+    for (int i = 0; i < P.n && P.tr2_ok; ++i) {
+        const double dl = abs_ad * P.rad[i];
+        dd e;
+        double mag;  // |tau| or |s|
+        if (i < P.r) {
+            const dd tau = a_d * P.reals[i];
+            e = tau * tau;
+            mag = std::fabs(to_d(tau));
+            sum_err2 += dl * (2.0 * mag + dl);
+        } else {
+            const cdd &z = P.pairs[i - P.r];
+            const dd sr = a_d * z.re, si = a_d * z.im;
+            e = (sr * sr - si * si) * 2.0;
+            mag = std::hypot(to_d(sr), to_d(si));
+            sum_err2 += 2.0 * dl * (2.0 * mag + dl);
+        }
+        // rounding of e in double-double is relative to the squares it sums
+        // (|s|^2 for a pair, whose two squares may cancel)
+        const double sq = 2.0 * mag * mag;
+        if (!(sq < std::ldexp(1.0, 52))) P.tr2_ok = false;  // frac(e) would carry too few bits
+        sum_e += sq;
+        P.v2.push_back(weight_of(e));
+    }
+    if (P.tr2_ok) {
+        const double E2d = std::ldexp(2.0 * sum_err2 + sum_e * std::ldexp(1.0, -100), 64);
+        if (!(E2d < std::ldexp(1.0, 31))) {
+            P.tr2_ok = false;
+        } else {
+            const uint64_t E2 = (uint64_t)std::ceil(E2d) + 2 * (uint64_t)P.n + 2;
+            P.t2_lo = (uint64_t)P.n + E2;
+            P.t2_hi = E2;
+        }
+    }
     return RFR_OK;
 }
 

@@ -47,6 +47,13 @@ struct Prepared {
     std::vector<cdd> pairs;       // c conjugate-pair representatives (Im > 0), by (Re, Im)
     std::vector<uint64_t> w;      // n weights, canonical element order
     uint64_t t_lo = 0, t_hi = 0;  // accept window
+    // second trace (Section 2: sum of squares of the monic-transform roots, an
+    // integer for every true factor): per-element weights floor(frac(e_i) 2^64)
+    // with e_i = (a_d u)^2 or 2 Re((a_d z)^2), and their window, like w/t_lo/t_hi;
+    // tr2_ok is false when the squares are too large for the weights' precision
+    std::vector<uint64_t> v2;
+    uint64_t t2_lo = 0, t2_hi = 0;
+    bool tr2_ok = false;
     std::vector<double> rad;      // n inclusion radii (a pair: the larger of its two discs)
     std::vector<std::vector<int64_t>> peeled;  // factors of single elements split off before the search
 };
@@ -56,6 +63,7 @@ struct Factored {
     int64_t content = 1;
     std::vector<std::vector<int64_t>> factors;  // canonical order
     uint64_t n_candidates = 0, n_confirmed = 0;
+    int trace_folded = 0;  // 1: the search folded the second trace into the weights
 };
 
 // Split content, sign and x-power; validate.  Section 2 preconditions.

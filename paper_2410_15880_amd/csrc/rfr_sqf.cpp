@@ -380,6 +380,7 @@ rfr_status factor_sqf_route(const int64_t *coeffs, int degree, const FactorOne &
         P.r += r->n_real;
         F.n_candidates += r->n_candidates;
         F.n_confirmed += r->n_confirmed;
+        F.trace_folded |= r->trace_folded;
         if (r->n_elements > nmax) {
             nmax = r->n_elements;
             P.t_lo = r->t_lo;

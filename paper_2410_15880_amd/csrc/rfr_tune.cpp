@@ -32,14 +32,15 @@ static bool load_table(const char *path) {
     int loaded = 0;
     while (std::fgets(line, sizeof line, f)) {
         if (line[0] == '#') continue;
-        int lg, b1, sub;
+        int lg, b1, sub, design = 0;
         double ms;
-        if (std::sscanf(line, "%d %d %d %lf", &lg, &b1, &sub, &ms) != 4 || lg < 0 || lg > dev::MAX_HALF) continue;
+        const int got = std::sscanf(line, "%d %d %d %lf %d", &lg, &b1, &sub, &ms, &design);
+        if (got < 4 || lg < 0 || lg > dev::MAX_HALF) continue;
         if (b1 >= 0 && b1 <= dev::MAXB1_LOG && sub >= dev::SUB_LOG_MIN && sub <= dev::SUB_LOG) {
-            set_tune(lg, Tune{b1, sub, ms});
+            set_tune(lg, Tune{b1, sub, ms, design == 1 ? 1 : 0});
             ++loaded;
         } else if (b1 == -1 && sub == -1) {  // back to the fixed rule
-            set_tune(lg, Tune{-1, -1, 0.0});
+            set_tune(lg, Tune{-1, -1, 0.0, 0});
             ++loaded;
         }
     }
@@ -87,14 +88,16 @@ extern "C" rfr_status rfr_autotune(rfr_ctx *ctx, int lg_lo, int lg_hi, const cha
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(RFR_EDEVICE, "hipEventCreate failed");
-    std::string table = "# rfr autotune table: lg b1 sub_log ms (larger half 2^lg keys; time of one search)\n";
+    std::string table =
+        "# rfr autotune table: lg b1 sub_log ms design (larger half 2^lg keys; time of one search;\n"
+        "# design 1: the query design, Algorithm E, was faster than the best split)\n";
     rfr_status st = RFR_OK;
     for (int lg = lg_lo; lg <= lg_hi && st == RFR_OK; ++lg) {
         const int n = 2 * lg + 1;  // halves of 2^lg keys each
         uint64_t seed = 0x5EED0000ull + (uint64_t)lg;
         std::vector<uint64_t> w(n);
         for (auto &x : w) x = splitmix64(seed);
-        Tune best{-1, -1, 1e30};
+        Tune best{-1, -1, 1e30, 0};
         for (int sub = dev::SUB_LOG_MIN; sub <= dev::SUB_LOG; ++sub) {
             const int LB = lg > sub ? lg - sub : 0;
             // level-1 buckets much larger than the level-2 digit range only
@@ -102,7 +105,7 @@ extern "C" rfr_status rfr_autotune(rfr_ctx *ctx, int lg_lo, int lg_hi, const cha
             const int lo = std::max({0, LB - dev::MAXB2_LOG, (LB + 1) / 2 - 2});
             const int hi = std::min(LB, dev::MAXB1_LOG);
             for (int b1 = lo; b1 <= hi; ++b1) {
-                set_tune(lg, Tune{b1, sub, 0.0});
+                set_tune(lg, Tune{b1, sub, 0.0, 0});
                 rfr_status e = ensure_workspace(ctx, s, recombine_workspace(n));
                 if (e != RFR_OK) {
                     st = e;
@@ -123,12 +126,35 @@ extern "C" rfr_status rfr_autotune(rfr_ctx *ctx, int lg_lo, int lg_hi, const cha
                     (void)hipEventElapsedTime(&ms, e0, e1);
                     if (rep > 0) t = std::min(t, (double)ms);  // first run warms up
                 }
-                if (t < best.ms) best = Tune{b1, sub, t};
+                if (t < best.ms) best = Tune{b1, sub, t, 0};
+            }
+        }
+        // the query design over the same weights (halves of at most 2^E_MAX_HALF keys)
+        if (st == RFR_OK && lg <= E_MAX_HALF) {
+            rfr_status e = ensure_workspace(ctx, s, recombine_e_workspace(n));
+            double t = 1e30;
+            std::string err;
+            for (int rep = 0; rep < 4 && e == RFR_OK; ++rep) {
+                (void)hipEventRecord(e0, s.stream);
+                rfr_status r = enqueue_recombine_e(w.data(), n, (uint64_t)n + 5, 5, s.ws, s.ws_bytes, s.stream,
+                                                   s.cand_dev, s.cap, s.count_dev, err);
+                (void)hipEventRecord(e1, s.stream);
+                if (r != RFR_OK || hipEventSynchronize(e1) != hipSuccess) {
+                    st = fail(RFR_EDEVICE, "query design failed while tuning: " + err);
+                    break;
+                }
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (rep > 0) t = std::min(t, (double)ms);
+            }
+            if (t < best.ms) {
+                best.design = 1;
+                best.ms = t;
             }
         }
         set_tune(lg, best);
         char buf[96];
-        std::snprintf(buf, sizeof buf, "%d %d %d %.4f\n", lg, best.b1, best.sub_log, best.ms);
+        std::snprintf(buf, sizeof buf, "%d %d %d %.4f %d\n", lg, best.b1, best.sub_log, best.ms, best.design);
         table += buf;
     }
     (void)hipEventDestroy(e0);

@@ -143,6 +143,59 @@ def test_search_capacity_overflow_reported(R):
     assert e.value.name == "RFR_ECANDIDATES"
 
 
+# ------------------------------------------------------------------ Algorithm E (query design)
+
+
+@pytest.mark.parametrize("n", [3, 4, 6, 9, 12, 17, 23, 26])
+def test_query_design_matches_bruteforce(R, n):
+    # Section 3.5: B' expanded, sorted and laid out as the splat table, every
+    # A sum generated and queried -- the same pattern set as Algorithm A
+    rng = random.Random(300 + n)
+    w = planted_weights(rng, n)
+    for t_lo, t_hi in [(0, 0), (n + 5, 3), (1 << 20, 1 << 18)]:
+        say("query design n=%d window=(%d,%d)" % (n, t_lo, t_hi))
+        got = R.recombine_e_dev(w, t_lo, t_hi, cap=1 << 16)
+        assert got == O.search_brute(w, t_lo, t_hi)
+
+
+@pytest.mark.parametrize("n", [30, 33, 38, 45])
+def test_query_design_matches_hs_oracle_and_hs_kernels(R, n):
+    rng = random.Random(2000 + n)
+    w = planted_weights(rng, n, k_rel=4)
+    t_lo, t_hi = n + 7, 5
+    say("query design n=%d" % n)
+    got = R.recombine_e_dev(w, t_lo, t_hi, cap=1 << 12)
+    assert got == R.recombine_dev(w, t_lo, t_hi, cap=1 << 12)
+    if n <= 38:
+        assert got == O.search_hs(w, t_lo, t_hi)
+
+
+def test_query_design_wraps_and_closed_forms(R):
+    for n in (10, 25, 31):
+        rng = random.Random(77 + n)
+        w = [rng.getrandbits(64) for _ in range(n)]
+        w[0] = (MASK - 2)           # pattern {0} sums to -3
+        w[2] = 4                    # pattern {2} sums to +4
+        w[3] = (1 << 63) - 1
+        w[4] = (1 << 63) + 3        # {3,4} sums to +2
+        w[n - 2] = MASK             # a B' value at the top of the table
+        say("query design wrap n=%d" % n)
+        for t_lo, t_hi in [(3, 4), (2, 3), (100, 100)]:
+            assert R.recombine_e_dev(w, t_lo, t_hi, cap=1 << 12) == O.search_hs(w, t_lo, t_hi)
+    n = 12
+    assert R.recombine_e_dev([0] * n, 0, 0, cap=4096) == list(range(1, 1 << (n - 1)))
+    rng = random.Random(5)
+    w = [rng.getrandbits(64) for _ in range(n)]
+    w[1] = (-w[0]) & MASK
+    assert R.recombine_e_dev(w, 0, 0) == [0b11]
+    assert R.recombine_e_dev([1 << i for i in range(n)], 0, 0) == []
+    # B' sums too clustered for the expansion's sort: reported, not searched
+    assert R.recombine_e_dev([0] * 30, 0, 0, cap=1 << 10) is None
+    with pytest.raises(R.RFRError) as e:
+        R.recombine_e_dev([0] * 14, 0, 0, cap=100)
+    assert e.value.name == "RFR_ECANDIDATES"
+
+
 # ------------------------------------------------------------------ end to end
 
 
@@ -429,3 +482,66 @@ def test_maximum_size_search_recovers_planted_factors(R):
     # search cannot reach n = 65): the two factors are irreducible
     say("  sympy factor_list of the degree-%d product" % (len(p) - 1))
     assert (r["content"], r["factors"]) == _sympy_factor(p)
+
+
+def test_seventy_element_search_streams_half_a(R):
+    # n = 70: half A holds 35 weights, beyond what one enumeration takes, so
+    # it is always streamed in chunks against the resident half B' (2^34 keys,
+    # about 220 GB of tables).  Beyond the oracle's reach: properties that hold
+    # at any size -- every planted relation is found, and every reported
+    # pattern's sum lies in the window (Python integers).  With a zero window
+    # the 2^69 patterns leave about 32 random ones beside the planted.
+    import torch
+    n = 70
+    rng = random.Random(7070)
+    w = [rng.getrandbits(64) for _ in range(n)]
+    planted = []
+    for k in range(3):
+        idx = sorted(rng.sample(range(n - 1), 5))
+        w[idx[-1]] = (-sum(w[i] for i in idx[:-1])) & MASK
+        planted.append(sum(1 << i for i in idx))
+    free_b = torch.cuda.mem_get_info()[0]
+    ws_b = min(R.lib().rfr_recombine_workspace_bytes(n), free_b - (8 << 30))
+    ws_b = max(R.lib().rfr_recombine_min_workspace_bytes(n), ws_b)
+    say("seventy elements: workspace %.0f GB" % (ws_b / 2 ** 30))
+    try:
+        got = R.recombine_dev(w, 0, 0, cap=1 << 12, ws_bytes=ws_b)
+    finally:
+        # hand the workspace back to the device (later tests allocate through HIP)
+        torch.cuda.empty_cache()
+    say("  %d patterns" % len(got))
+    assert all(p in got for p in planted if p < (1 << (n - 1)))
+    for p in got:
+        assert sum(w[i] for i in range(n - 1) if (p >> i) & 1) & MASK == 0
+    assert len(got) < 200
+
+
+def test_flood_inputs_fold_the_second_trace(R, ctx):
+    # Swinnerton-Dyer f_5 (1.57M patterns whose root sum is an integer) and
+    # f_5 * (x^32 - x - 1) (3.14M): the first search overflows the candidate
+    # capacity, the second folds the second trace into the weights and keeps
+    # only the patterns whose sum of squares is an integer as well.  Results
+    # against the oracle's stored ones (make_golden.py flood).
+    g = json.load(open(os.path.join(HERE, "golden", "golden_flood.json")))["cases"]
+    ws = W.config_flood()
+    for w in ws:
+        e = g[str(w.seed)]
+        say("flood input seed %d, degree %d" % (w.seed, w.degree))
+        r = ctx.factor_full(w.coeffs)
+        assert (r["content"], r["factors"]) == (e["content"], [tuple(f) for f in e["factors"]])
+        assert r["n"] == e["n"]
+        assert r["trace_folded"] == 1
+        assert e["tr2_candidates"] <= r["n_candidates"] < e["tr2_candidates"] + 64
+        say("  first-trace candidates %d (oracle), after the second trace %d on the device (oracle %d): "
+            "%d rejected inside the search; search %.1f ms" % (
+                e["tr1_candidates"], r["n_candidates"], e["tr2_candidates"],
+                e["tr1_candidates"] - r["n_candidates"], r["ms_search"]))
+    # the same inputs inside a batch (their batch slots overflow, then the
+    # plain path folds) and an input that needs no folding
+    polys = [w.coeffs for w in ws] + [W.config_small().coeffs]
+    got = ctx.factor_batch(polys)
+    for w, r in zip(ws, got):
+        e = g[str(w.seed)]
+        assert r == (e["content"], [tuple(f) for f in e["factors"]])
+    assert got[-1] == O.factor(W.config_small().coeffs)
+    assert ctx.factor_full(W.config_small().coeffs)["trace_folded"] == 0
