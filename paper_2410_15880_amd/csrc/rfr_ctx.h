@@ -52,6 +52,7 @@ struct Request {
 };
 
 struct BatchState;  // persistent-kernel batch resources (rfr_batch.cpp)
+struct BigJob;      // serving: a prepared search waiting for slot 0 (rfr_serve.cpp)
 
 }  // namespace rfr
 
@@ -71,6 +72,11 @@ struct rfr_ctx {
     std::deque<rfr::Request *> queue;
     std::map<uint64_t, rfr::Request *> reqs;
     int big_running = 0;         // admitted searches that fill the GPU on their own
+    std::deque<rfr::BigJob *> big_jobs;  // serving: handed-off searches for slot 0, in arrival order
+    std::vector<std::thread> big_workers;
+    std::condition_variable cv_big;
+    bool big_stopping = false;
+    int n_big = 0;                     // serving: 1 when slot 0 takes the searches that fill the GPU
     hipStream_t lane_big = nullptr;    // serving: the stream of the searches that fill the GPU
     hipStream_t lane_small = nullptr;  // serving: the stream of every other request's device work
     uint64_t next_ticket = 1;
