@@ -48,7 +48,7 @@ constexpr int MAX_HALF = 34;      // elements per enumerated half (2^34 keys)
 constexpr int MAX_SEARCH_N = 2 * MAX_HALF + 2;  // elements of a search (n - 1 = 69 leaves half A
                                   // 35 weights: it is then streamed in at least 2 chunks)
 constexpr int MAX_CHUNK_BITS = 8; // half A streamed in at most 2^8 chunks
-constexpr int RECOVER_FEW = 64;   // candidate keys handled by the meet-in-the-middle recovery
+constexpr int RECOVER_FEW = 128;  // candidate key pairs handled by the meet-in-the-middle recovery
 constexpr int SPT4 = 16;          // Gray steps per thread in that recovery
 
 struct HalfArgs {

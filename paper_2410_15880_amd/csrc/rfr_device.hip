@@ -228,11 +228,13 @@ __global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(2))) void k
     // Tiles start at multiples of KPT steps, so inside a tile step k + 1 flips
     // bit ctz(k + 1) < log2 KPT: those weights sit in registers and only the
     // step into the next tile reads its weight by a computed index.  The count
-    // pass, which keeps no tile in LDS, walks 16 steps at a time: half the
-    // registers of the keys, more waves in flight (measured 0.064 against
-    // 0.076 ms per degree-100 search); the partition pass keeps KPT1-step tiles,
-    // whose longer runs per bucket store faster than more waves would gain.
-    constexpr int KPT = COUNT ? 16 : KPT1;
+    // pass, which keeps no tile in LDS, walks 16 steps at a time into at most
+    // 256 buckets: half the registers of the keys, more waves in flight
+    // (measured 0.064 against 0.076 ms per degree-100 search; with 2048
+    // buckets, where its LDS counters are contended, 8.1 against 5.1 ms at
+    // n = 65); the partition pass keeps KPT1-step tiles, whose longer runs per
+    // bucket store faster than more waves would gain.
+    constexpr int KPT = COUNT && NBMAX == NT1 ? 16 : KPT1;
     constexpr int LOGK = __builtin_ctz(KPT);
     static_assert((1 << LOGK) == KPT && (KPT1 * TILES1) % KPT == 0, "tiles of a power-of-two number of Gray steps");
     const int mh = H.m - H.L;
@@ -1119,9 +1121,17 @@ __global__ __launch_bounds__(NT1) void k_recover_few(JobArgs Jarg, Multi M) {
     __shared__ uint64_t s_v[256], s_sorted[256];
     __shared__ uint32_t s_lane[256];
     __shared__ uint64_t s_list[RECOVER_FEW];
+    __shared__ uint8_t s_dup[RECOVER_FEW];
     if (tid < H.m) s_w[tid] = J.wts[half][tid];
-    if (tid < cnt) s_list[tid] = J.kp[2 * tid + half];
+    for (uint32_t i = tid; i < cnt; i += NT1) s_list[i] = J.kp[2 * i + half];
     __syncthreads();
+    // the same key listed twice (it pairs with several keys of the other
+    // half) is recorded once: flag the repeats once, not at every step
+    for (uint32_t i = tid; i < cnt; i += NT1) {
+        bool dup = false;
+        for (uint32_t c2 = 0; c2 < i && !dup; ++c2) dup = s_list[c2] == s_list[i];
+        s_dup[i] = dup;
+    }
     if (tid < nl) {
         uint64_t v = J.kbase[half];
         for (int i = 0; i < H.L; ++i)
@@ -1148,6 +1158,7 @@ __global__ __launch_bounds__(NT1) void k_recover_few(JobArgs Jarg, Multi M) {
         if ((g >> i) & 1) shi += s_w[H.L + i];
     for (uint64_t h = h0; h < h1; ++h) {
         for (uint32_t c = 0; c < cnt; ++c) {
+            if (s_dup[c]) continue;
             const uint64_t key = s_list[c];
             const uint64_t x = key - shi;
             int lo = 0, hi = nl;
@@ -1156,9 +1167,7 @@ __global__ __launch_bounds__(NT1) void k_recover_few(JobArgs Jarg, Multi M) {
                 if (s_sorted[mid] < x) lo = mid + 1;
                 else hi = mid;
             }
-            bool dup = false;  // the same key listed twice: record it once
-            for (uint32_t c2 = 0; c2 < c && !dup; ++c2) dup = s_list[c2] == key;
-            for (int q = lo; !dup && q < nl && s_sorted[q] == x; ++q) {
+            for (int q = lo; q < nl && s_sorted[q] == x; ++q) {
                 const uint64_t pat = ((uint64_t)s_lane[q] | (g << H.L)) | J.pbase[half];
                 const uint64_t r = atomicAdd((unsigned long long *)&J.rec_count[half], 1ull);
                 if (r < J.kcap) {

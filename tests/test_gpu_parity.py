@@ -344,6 +344,24 @@ def test_many_patterns_per_candidate_key(R):
     assert e.value.name == "RFR_ECANDIDATES"
 
 
+@pytest.mark.parametrize("n,expect", [(41, 100), (43, 700)])
+def test_recovery_of_many_candidate_keys(R, n, expect):
+    # random weights with a window wide enough for about `expect` false
+    # candidates (2^(n-1) patterns, each in the window with probability
+    # width / 2^64; the window stays below 2^32): about 100 key pairs take the
+    # meet-in-the-middle recovery of the few-candidate path, about 700 the
+    # re-enumeration against a key bitmap.  Both must return the oracle's
+    # Horowitz-Sahni candidates.
+    rng = random.Random(7300 + expect)
+    w = [rng.getrandbits(64) for _ in range(n)]
+    t = (expect << 64) // (1 << (n - 1)) // 2
+    say("many candidate keys: about %d" % expect)
+    got = R.recombine_dev(w, t, t, cap=1 << 14)
+    want = O.search_hs(w, t, t)
+    assert expect // 2 < len(want) < expect * 2
+    assert got == want
+
+
 def test_small_budget_context_streams_half_a(R):
     # a budget below the full tables of the degree-60 searches: the plain path
     # streams half A and still returns the oracle's factorisations
