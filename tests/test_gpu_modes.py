@@ -150,3 +150,43 @@ def test_served_alone_equals_in_mix(R):
             say("  sympy factor_list, degree", r.work.degree)
             assert got == _sympy_factor(r.work.coeffs), r.work.seed
     assert pinned == len(reqs) - 2
+
+
+def test_served_small_requests_pass_queued_big_searches(R):
+    # Eight degree-100 requests (searches with halves of 2^25..2^27 keys, which
+    # run one at a time on the big-search slot) are submitted, then twelve
+    # degree-30 ones, to a server with two host workers.  The workers must hand
+    # the big searches over and go on with the small requests, so that those
+    # finish while the big searches still queue (workers that waited for the
+    # slot would hold the small ones back behind the whole queue).  Every
+    # result must equal the same request's standalone result.
+    bigs = [w.coeffs for w in W.config_large(count=8)]
+    smalls = [W.rand_poly(W._rng(8800 + i), 30, -1000, 1000) for i in range(12)]
+    with R.Context(0) as ctx:
+        alone = [ctx.factor(p) for p in bigs + smalls]
+        ctx.serve_start(max_active=4, host_threads=2)
+        t0 = time.perf_counter()
+        subs, tickets = [], []
+        for p in bigs + smalls:
+            subs.append(time.perf_counter() - t0)
+            tickets.append(ctx.submit(p))
+        done = {}
+        deadline = time.time() + 60
+        while len(done) < len(tickets) and time.time() < deadline:
+            for t in tickets:
+                if t not in done:
+                    q = ctx.poll(t)
+                    if q is not None:
+                        done[t] = q
+            time.sleep(0.0005)
+        ctx.serve_stop()
+    assert len(done) == len(tickets)
+    fin = []
+    for t, s, a in zip(tickets, subs, alone):
+        res, lat = done[t]
+        assert not isinstance(res, Exception), res
+        assert (res["content"], res["factors"]) == a
+        fin.append(s + lat / 1000.0)
+    big_fin, small_fin = sorted(fin[:8]), sorted(fin[8:])
+    say("finish: median small %.2f ms, sixth of eight big %.2f ms" % (1e3 * small_fin[6], 1e3 * big_fin[5]))
+    assert small_fin[6] < big_fin[5]
