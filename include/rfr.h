@@ -150,7 +150,13 @@ rfr_status rfr_factor_batch(rfr_ctx *ctx, int count, const int64_t *coeffs,
 
 /* Start the serving loop on this context: up to `max_active` requests share
  * the device at once, each admitted when its search tables fit the memory
- * budget.  Requests are factored exactly as by rfr_factor. */
+ * budget.  `host_threads` workers find roots and weights and confirm
+ * candidates; with max_active > 1, searches with a half of 2^23 keys or more
+ * run one at a time on slot 0 (on a stream of their own, driven by two
+ * threads of the library) while the workers go on with other requests, whose
+ * device work runs on a second stream.  Requests are factored exactly as by
+ * rfr_factor.  Errors: RFR_EINVAL (max_active outside [1, 64], host_threads
+ * outside [1, 256]), RFR_EBUSY (already serving), RFR_EDEVICE, RFR_ENOMEM. */
 rfr_status rfr_serve_start(rfr_ctx *ctx, int max_active, int host_threads);
 
 /* Queue a request; returns a ticket.  Thread-safe.  The coefficient array is
