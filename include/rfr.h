@@ -196,8 +196,9 @@ rfr_status rfr_profile_read(rfr_ctx *ctx, rfr_profile_t *out);
 /* ------------------------------------------------------------------ tuning */
 
 /* Time the device search for every radix split candidate of each size class
- * lg in [lg_lo, lg_hi] (halves of 2^lg keys; 8 <= lg_lo <= lg_hi <= 28): the
- * sub-bucket size (2^9 or 2^10 keys) and the level-1 digit bits.  Installs
+ * lg in [lg_lo, lg_hi] (halves of 2^lg keys; 8 <= lg_lo <= lg_hi <= 32; lg = 32
+ * needs the tables of an n = 65 search, about 80 GB): the sub-bucket size
+ * (2^9 or 2^10 keys) and the level-1 digit bits.  Installs
  * the fastest split per class for this process and, if path_out is not NULL,
  * writes the table ("lg b1 sub_log ms" lines).  Not concurrent with other
  * calls.  Contexts load RFR_TUNING or the package's tuning/mi355x.txt at

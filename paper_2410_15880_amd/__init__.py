@@ -304,7 +304,9 @@ class Context:
 
     # ---- tuning
     def autotune(self, lg_lo: int = 12, lg_hi: int = 27, path: Optional[str] = None):
-        """Time every radix split per size class on this device; install the best."""
+        """Time every radix split per size class (halves of 2^lg keys, lg in
+        [8, 32]; lg = 32 needs about 80 GB of tables) on this device; install
+        the best."""
         _check(lib().rfr_autotune(self._h, lg_lo, lg_hi, path.encode() if path else None))
 
     def set_design(self, design: int):

@@ -81,7 +81,9 @@ extern "C" rfr_status rfr_load_tuning(const char *path) {
 }
 
 extern "C" rfr_status rfr_autotune(rfr_ctx *ctx, int lg_lo, int lg_hi, const char *path_out) {
-    if (!ctx || lg_lo < 8 || lg_hi > 28 || lg_lo > lg_hi) return fail(RFR_EINVAL, "need 8 <= lg_lo <= lg_hi <= 28");
+    // lg = 32 times searches over n = 65 weights (both halves 2^32 keys, about
+    // 80 GB of tables); larger classes would not fit twice in one GPU's memory
+    if (!ctx || lg_lo < 8 || lg_hi > 32 || lg_lo > lg_hi) return fail(RFR_EINVAL, "need 8 <= lg_lo <= lg_hi <= 32");
     if (ctx->serving) return fail(RFR_EBUSY, "stop serving before tuning");
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(RFR_EDEVICE, "hipSetDevice failed");
     Slot &s = ctx->main;
