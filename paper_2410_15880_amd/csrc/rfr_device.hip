@@ -1242,17 +1242,52 @@ __global__ __launch_bounds__(NT1) void k_recover(JobArgs Jarg, Multi M) {
     uint64_t slo = J.kbase[half];
     for (int i = 0; i < H.L; ++i)
         if ((tid >> i) & 1) slo += s_w[i];
-    const uint64_t h0 = (uint64_t)wg * H.spw;
-    const uint64_t h1 = min(h0 + (uint64_t)H.spw, H.steps);
-    uint64_t g = h0 ^ (h0 >> 1);
-    uint64_t shi = 0;
-    for (int i = 0; i < H.m - H.L; ++i)
-        if ((g >> i) & 1) shi += s_w[H.L + i];
-    for (uint64_t h = h0; h < h1; ++h) {
-        const uint64_t key = slo + shi;
-        if (act) {
-            const uint32_t hb = (uint32_t)(key >> (64 - RBITS_LOG));
-            if ((s_bits[hb >> 5] >> (hb & 31)) & 1) {
+    constexpr int KPT = 16;
+    constexpr int LOGK = 4;
+    static_assert((1 << LOGK) == KPT && (KPT1 * TILES1) % KPT == 0, "ranges of whole tiles");
+    const int mh = H.m - H.L;
+    uint64_t wlow[LOGK];
+#pragma unroll
+    for (int i = 0; i < LOGK; ++i) wlow[i] = mh > i ? s_w[H.L + i] : 0;
+    // A single search's grid is capped (RECOVER_WGS per half): the table
+    // above is built once per workgroup, which then walks every gridDim.x-th
+    // range of spw Gray steps.  A multi-job launch has one range per block.
+    for (uint32_t w = wg; w < H.nwg1; w += MULTI ? H.nwg1 : gridDim.x) {
+        const uint64_t h0 = (uint64_t)w * H.spw;
+        const uint64_t h1 = min(h0 + (uint64_t)H.spw, H.steps);
+        uint64_t g = h0 ^ (h0 >> 1);
+        uint64_t shi = 0;
+        for (int i = 0; i < H.m - H.L; ++i)
+            if ((g >> i) & 1) shi += s_w[H.L + i];
+        // tiles of KPT steps (the ranges start at multiples of spw, a multiple
+        // of KPT): inside a tile step k + 1 flips bit ctz(k + 1) < log2 KPT,
+        // whose weight sits in a register, so only the step into the next
+        // tile reads its weight from LDS.  The tile only tests the prefix
+        // bitmap; the rare keys that pass are rebuilt from their step's Gray
+        // code and looked up afterwards.
+        for (uint64_t h = h0; h < h1; h += KPT) {
+            const int ns = (int)min((uint64_t)KPT, h1 - h);
+            uint32_t hitm = 0;
+#pragma unroll
+            for (int k = 0; k < KPT; ++k) {
+                const uint64_t key = slo + shi;
+                const uint32_t hb = (uint32_t)(key >> (64 - RBITS_LOG));
+                hitm |= (uint32_t)(act && k < ns && ((s_bits[hb >> 5] >> (hb & 31)) & 1)) << k;
+                const uint64_t t = h + k + 1;
+                if (k < ns && t < h1) {
+                    const int bb = k < KPT - 1 ? __builtin_ctz(k + 1) : __builtin_ctzll(t);
+                    const uint64_t wb = k < KPT - 1 ? wlow[__builtin_ctz(k + 1) % LOGK] : s_w[H.L + bb];
+                    g ^= 1ull << bb;
+                    shi += ((g >> bb) & 1) ? wb : (0 - wb);
+                }
+            }
+            while (hitm) {
+                const int k = __builtin_ctz(hitm);
+                hitm &= hitm - 1;
+                const uint64_t gk = (h + k) ^ ((h + k) >> 1);
+                uint64_t key = slo;
+                for (int i = 0; i < mh; ++i)
+                    if ((gk >> i) & 1) key += s_w[H.L + i];
                 uint32_t lo = 0, len = (uint32_t)cnt;  // first of s_list[0, cnt) not below key
                 while (len > 0) {
                     const uint32_t half_len = len >> 1;
@@ -1264,7 +1299,7 @@ __global__ __launch_bounds__(NT1) void k_recover(JobArgs Jarg, Multi M) {
                     }
                 }
                 if (lo < cnt && s_list[lo] == key) {
-                    const uint64_t pat = ((uint64_t)tid | (g << H.L)) | J.pbase[half];
+                    const uint64_t pat = ((uint64_t)tid | (gk << H.L)) | J.pbase[half];
                     const uint64_t r = atomicAdd((unsigned long long *)&J.rec_count[half], 1ull);
                     if (r < J.kcap) {
                         J.rec[((size_t)half * J.kcap + r) * 2] = key;
@@ -1272,13 +1307,6 @@ __global__ __launch_bounds__(NT1) void k_recover(JobArgs Jarg, Multi M) {
                     }
                 }
             }
-        }
-        const uint64_t t = h + 1;
-        if (t < h1) {
-            const int bb = __builtin_ctzll(t);
-            g ^= 1ull << bb;
-            const uint64_t wb = s_w[H.L + bb];
-            shi += ((g >> bb) & 1) ? wb : (0 - wb);
         }
     }
 }
@@ -1308,26 +1336,44 @@ __global__ __launch_bounds__(NT1) void k_pairs(JobArgs Jarg, Multi M) {
         return;
     }
     const uint32_t ra = (uint32_t)min(J.rec_count[0], J.kcap), rb = (uint32_t)min(J.rec_count[1], J.kcap);
-    for (uint32_t p = threadIdx.x; p < cnt; p += NT1) {
-        const uint64_t a = J.kp[2 * p], bk = J.kp[2 * p + 1];
-        bool first = true;
-        for (uint32_t q = 0; q < p && first; ++q)
-            if (J.kp[2 * q] == a && J.kp[2 * q + 1] == bk) first = false;
-        if (!first) continue;
-        for (uint32_t x = 0; x < ra; ++x) {
-            if (J.rec[2 * x] != a) continue;
-            const uint64_t pa = J.rec[2 * x + 1];
-            for (uint32_t y = 0; y < rb; ++y) {
-                if (J.rec[((size_t)J.kcap + y) * 2] != bk) continue;
-                const uint64_t pb = J.rec[((size_t)J.kcap + y) * 2 + 1];
-                if (pa == 0 && pb == 0) continue;  // the empty pattern s = 0
-                const unsigned long long o = atomicAdd((unsigned long long *)&s_total, 1ull);
-                if (o < J.cap) {
-                    J.out[2 * o] = pa;
-                    J.out[2 * o + 1] = pb;
+    // every distinct key pair (a, b') against the (key, pattern) records of
+    // both halves; key(p, i) / rec_a(x) / rec_b(y) read the staged copies in
+    // LDS for a single search (its one workgroup holds them all) and global
+    // memory for a multi-job launch, whose many blocks keep a small footprint
+    auto pairs = [&](auto key, auto rec_a, auto rec_b) {
+        for (uint32_t p = threadIdx.x; p < cnt; p += NT1) {
+            const uint64_t a = key(p, 0), bk = key(p, 1);
+            bool first = true;
+            for (uint32_t q = 0; q < p && first; ++q)
+                if (key(q, 0) == a && key(q, 1) == bk) first = false;
+            if (!first) continue;
+            for (uint32_t x = 0; x < ra; ++x) {
+                if (rec_a(x) != a) continue;
+                const uint64_t pa = J.rec[2 * x + 1];
+                for (uint32_t y = 0; y < rb; ++y) {
+                    if (rec_b(y) != bk) continue;
+                    const uint64_t pb = J.rec[((size_t)J.kcap + y) * 2 + 1];
+                    if (pa == 0 && pb == 0) continue;  // the empty pattern s = 0
+                    const unsigned long long o = atomicAdd((unsigned long long *)&s_total, 1ull);
+                    if (o < J.cap) {
+                        J.out[2 * o] = pa;
+                        J.out[2 * o + 1] = pb;
+                    }
                 }
             }
         }
+    };
+    if constexpr (!MULTI) {
+        __shared__ uint64_t s_kp[2 * KCAP_MAX], s_ra[KCAP_MAX], s_rb[KCAP_MAX];
+        for (uint32_t i = threadIdx.x; i < 2 * cnt; i += NT1) s_kp[i] = J.kp[i];
+        for (uint32_t i = threadIdx.x; i < ra; i += NT1) s_ra[i] = J.rec[2 * i];
+        for (uint32_t i = threadIdx.x; i < rb; i += NT1) s_rb[i] = J.rec[((size_t)J.kcap + i) * 2];
+        __syncthreads();
+        pairs([&](uint32_t p, int h) { return s_kp[2 * p + h]; }, [&](uint32_t x) { return s_ra[x]; },
+              [&](uint32_t y) { return s_rb[y]; });
+    } else {
+        pairs([&](uint32_t p, int h) { return J.kp[2 * p + h]; }, [&](uint32_t x) { return J.rec[2 * x]; },
+              [&](uint32_t y) { return J.rec[((size_t)J.kcap + y) * 2]; });
     }
     __syncthreads();
     if (threadIdx.x == 0) *J.out_count = s_total > J.cap ? ~0ull : s_total;
@@ -1553,7 +1599,8 @@ static hipError_t launch_all(const JobArgs &J, const Multi &M, const uint32_t *g
     hipLaunchKernelGGL((k_join<false, MULTI>), gj, dim3(NT3), 0, st, J, M, (uint64_t *)nullptr);
     rec(5);
     hipLaunchKernelGGL((k_recover_few<MULTI>), dim3(grids[ST_RFEW], 2), dim3(NT1), 0, st, J, M);
-    hipLaunchKernelGGL((k_recover<MULTI>), dim3(grids[ST_RMANY], 2), dim3(NT1), 0, st, J, M);
+    hipLaunchKernelGGL((k_recover<MULTI>), dim3(MULTI ? grids[ST_RMANY] : std::min(grids[ST_RMANY], (uint32_t)RECOVER_WGS), 2),
+                       dim3(NT1), 0, st, J, M);
     hipLaunchKernelGGL((k_pairs<MULTI>), dim3(grids[ST_PAIRS]), dim3(NT1), 0, st, J, M);
     rec(6);
     return hipGetLastError();
@@ -2268,7 +2315,8 @@ rfr_status enqueue_recombine_e(const uint64_t *w, int n, uint64_t t_lo, uint64_t
     hipLaunchKernelGGL(k_query, dim3(ha.nwg1), dim3(NT1), 0, st, J, S);
     const uint32_t rfew = (uint32_t)((std::max(ha.steps, hb.steps) + (uint64_t)NT1 * SPT4 - 1) / ((uint64_t)NT1 * SPT4));
     hipLaunchKernelGGL((k_recover_few<false>), dim3(rfew, 2), dim3(NT1), 0, st, J, M);
-    hipLaunchKernelGGL((k_recover<false>), dim3(std::max(ha.nwg1, hb.nwg1), 2), dim3(NT1), 0, st, J, M);
+    hipLaunchKernelGGL((k_recover<false>), dim3(std::min(std::max(ha.nwg1, hb.nwg1), (uint32_t)RECOVER_WGS), 2),
+                       dim3(NT1), 0, st, J, M);
     hipLaunchKernelGGL((k_pairs<false>), dim3(1), dim3(NT1), 0, st, J, M);
     if (hipGetLastError() != hipSuccess) {
         err = "kernel launch failed";
