@@ -243,10 +243,11 @@ def served_leg(R, W, ctx, count=1000, warm=100, rhos=(0.5, 0.8, 2.0), max_active
     batching, against plain rfr_factor calls one at a time on the same stream.
 
     Plain capacity is measured by factoring every request one after another
-    (a FIFO server that never idles); its latencies at rate lambda follow from
-    those measured service times and the arrival times (exact for one server).
-    Served runs submit at the arrival times.  At rho above 1 both systems are
-    saturated, so the served throughput there is its capacity."""
+    (a FIFO server that never idles).  At each rate the plain FIFO server is
+    then run: one rfr_factor call after another, each request waiting for its
+    arrival time.  Served runs submit at the same arrival times.  At rho above
+    1 both systems are saturated, so the served throughput there is its
+    capacity."""
     total = warm + count
     probe = W.config_stream(total, rate_per_s=1.0)
     for r in probe[:warm]:
@@ -278,10 +279,18 @@ def served_leg(R, W, ctx, count=1000, warm=100, rhos=(0.5, 0.8, 2.0), max_active
         log("served run at rho %.1f done" % rho)
         t_first = reqs[warm].t_arrive
         span = max(sub_t[k] + lat[k] / 1000.0 for k in range(count)) - sub_t[0]
-        fin, lat_fifo = 0.0, []
-        for r, sv in zip(reqs[warm:], service):
-            fin = max(fin, r.t_arrive - t_first) + sv
-            lat_fifo.append((fin - (r.t_arrive - t_first)) * 1000.0)
+        log("plain FIFO run at rho %.1f" % rho)
+        lat_fifo, t0 = [], time.perf_counter()
+        for r in reqs[warm:]:
+            arrive = r.t_arrive - t_first
+            while time.perf_counter() - t0 < arrive:
+                time.sleep(0.0002)
+            try:
+                ctx.factor(r.work.coeffs)
+            except R.RFRError:
+                pass
+            lat_fifo.append((time.perf_counter() - t0 - arrive) * 1000.0)
+        fin = time.perf_counter() - t0
         def outcome(x):
             return ("error", getattr(x, "status", None)) if isinstance(x, Exception) else \
                 (x["content"], x["factors"])
