@@ -393,6 +393,32 @@ def _restore_tuning(R, tmp_path, lgs):
         R.load_tuning(R.TUNING_PATH)
 
 
+def test_autotune_table_keeps_results(R, tmp_path):
+    # the tuner times every split of two size classes and writes its table;
+    # a table changes speed and workspace only, never a result (a degree-50
+    # input searches halves of 2^12..2^13 keys, the tuned classes)
+    p = W.rand_poly(W._rng(5050), 50, -1000, 1000)
+    e = O.factor(p)
+    out = tmp_path / "tuned.txt"
+    try:
+        with R.Context(0) as c:
+            assert c.factor(p) == e
+            say("autotune 12..13")
+            c.autotune(12, 13, str(out))
+            rows = [l.split() for l in out.read_text().splitlines() if l and not l.startswith("#")]
+            assert [int(r[0]) for r in rows] == [12, 13]
+            for r in rows:
+                assert len(r) == 5 and int(r[1]) >= 0 and 9 <= int(r[2]) <= 10 and float(r[3]) > 0
+                assert int(r[4]) in (0, 1)
+            assert c.factor(p) == e
+            with pytest.raises(R.RFRError) as err:
+                c.autotune(12, 33)
+            assert err.value.name == "RFR_EINVAL"
+    finally:
+        if os.path.exists(R.TUNING_PATH):
+            R.load_tuning(R.TUNING_PATH)
+
+
 def test_multi_chunk_gather_matches_oracle(R, tmp_path):
     lgs = [20, 21, 22]
     try:
