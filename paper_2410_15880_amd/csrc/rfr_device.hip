@@ -172,7 +172,7 @@ __global__ void k_init(JobArgs Jarg, Multi M) {
 // gray(h) = h ^ (h >> 1), so going from h to h+1 flips exactly bit ctz(h+1) and
 // changes the high sum by one wavefront-uniform +-w.
 template <bool COUNT, int NBMAX, bool MULTI>
-__global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(2))) void k_enum(JobArgs Jarg, Multi M) {
+__global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(!COUNT && NBMAX == NT1 ? 4 : 2))) void k_enum(JobArgs Jarg, Multi M) {
     const JobArgs *Jp;
     uint32_t wg;
     if (!pick<MULTI>(Jarg, M, COUNT ? ST_COUNT : ST_ENUM, Jp, wg)) return;
@@ -201,7 +201,20 @@ __global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(2))) void k
     __shared__ uint32_t s_off[NBMAX];
     __shared__ uint64_t s_cur[COUNT ? 1 : NBMAX];
     __shared__ uint64_t s_tmp[NT1 / 64 + 1];
-    __shared__ uint64_t s_buf[COUNT ? 1 : T1];
+    // With 2^8 buckets the partition pass keeps the tile in LDS as a
+    // permutation, not as keys: a key is its lane's low sum plus its step's
+    // high sum (the same for the whole workgroup), so sorted slot p holds
+    // (step << 8 | lane) and the store phase rebuilds the key from two small
+    // tables.  16 KB of LDS per tile instead of 64 KB and no keys held in
+    // registers: four workgroups per CU instead of two (0.306 -> 0.281 ms per
+    // degree-100 search).  With more buckets (2^12-2^17 keys per bucket in
+    // runs of a few keys) the tile of keys was faster and is kept.
+    constexpr bool PERM = !COUNT && NBMAX == NT1;
+    constexpr int KPTP = KPT1;  // Gray steps per partition tile
+    __shared__ uint64_t s_buf[COUNT || PERM ? 1 : T1];
+    __shared__ uint16_t s_perm[PERM ? NT1 * KPTP : 1];
+    __shared__ uint64_t s_slo[PERM ? NT1 : 1];
+    __shared__ uint64_t s_shi[PERM ? KPTP : 1];
 
     if (tid < H.m) s_w[tid] = J.wts[blockIdx.y][tid];
     for (int b = tid; b < nb; b += NT1) {
@@ -219,6 +232,7 @@ __global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(2))) void k
     uint64_t slo = J.kbase[blockIdx.y];
     for (int i = 0; i < H.L; ++i)
         if ((tid >> i) & 1) slo += s_w[i];
+    if (PERM && act) s_slo[tid] = slo;
     const uint64_t h0 = (uint64_t)wg * H.spw;
     const uint64_t h1 = min(h0 + (uint64_t)H.spw, H.steps);
     uint64_t g = h0 ^ (h0 >> 1);
@@ -235,6 +249,7 @@ __global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(2))) void k
     // n = 65); the partition pass keeps KPT1-step tiles, whose longer runs per
     // bucket store faster than more waves would gain.
     constexpr int KPT = COUNT && NBMAX == NT1 ? 16 : KPT1;
+    static_assert(COUNT || KPT == KPTP, "the partition pass's tables hold one tile");
     constexpr int LOGK = __builtin_ctz(KPT);
     static_assert((1 << LOGK) == KPT && (KPT1 * TILES1) % KPT == 0, "tiles of a power-of-two number of Gray steps");
     const int mh = H.m - H.L;
@@ -244,10 +259,21 @@ __global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(2))) void k
 
     for (uint64_t h = h0; h < h1; h += KPT) {
         const int ns = (int)min((uint64_t)KPT, h1 - h);
-        uint64_t key[KPT];
+        // each key's level-1 digit is counted (and, in the partition pass,
+        // ranked within its digit: d << 13 | rank, a tile holding at most 2^13
+        // keys and 2^12 digits) as the Gray walk produces it
+        uint32_t pk[COUNT ? 1 : KPT];
+        uint64_t key_s[COUNT || PERM ? 1 : KPT];  // the keys, for a tile of keys
 #pragma unroll
         for (int k = 0; k < KPT; ++k) {
-            key[k] = slo + shi;
+            const uint64_t key = slo + shi;
+            if constexpr (!COUNT && !PERM) key_s[k] = key;
+            if (act && k < ns) {
+                const uint32_t d = dig(key, sh1, m1);
+                if constexpr (COUNT) atomicAdd(&s_cnt[d], 1u);
+                else pk[k] = (d << 13) | atomicAdd(&s_cnt[d], 1u);
+            }
+            if (PERM && tid == 0 && k < ns) s_shi[k] = shi;  // the same for every lane
             const uint64_t t = h + k + 1;
             if (k < ns && t < h1) {
                 const int b = k < KPT - 1 ? __builtin_ctz(k + 1) : __builtin_ctzll(t);
@@ -256,16 +282,7 @@ __global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(2))) void k
                 shi += ((g >> b) & 1) ? wb : (0 - wb);
             }
         }
-        if (COUNT) {
-#pragma unroll
-            for (int k = 0; k < KPT; ++k)
-                if (act && k < ns) atomicAdd(&s_cnt[dig(key[k], sh1, m1)], 1u);
-            continue;
-        }
-        uint32_t rank[KPT];
-#pragma unroll
-        for (int k = 0; k < KPT; ++k)
-            if (act && k < ns) rank[k] = atomicAdd(&s_cnt[dig(key[k], sh1, m1)], 1u);
+        if constexpr (COUNT) continue;
         __syncthreads();
         if (NBMAX == NT1) {
             uint64_t tot;
@@ -281,8 +298,9 @@ __global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
         for (int k = 0; k < KPT; ++k)
             if (act && k < ns) {
-                const uint32_t d = dig(key[k], sh1, m1);
-                s_buf[s_off[d] + rank[k]] = key[k];
+                const uint32_t slot = s_off[pk[k] >> 13] + (pk[k] & 8191u);
+                if constexpr (PERM) s_perm[slot] = (uint16_t)((k << 8) | tid);
+                else s_buf[slot] = key_s[k];
             }
         // destination of tile slot p of bucket d: s_cur[d] - s_off[d] + p, the
         // cursor first stepping down by the run length when filling downwards
@@ -293,12 +311,19 @@ __global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(2))) void k
         // data and store nothing), then the stores; `keys_out` is a local so
         // that the stores do not make the compiler reload it from the argument
         // block between them
-#pragma unroll
-        for (int i0 = 0; i0 < KPT; i0 += 8) {
+        auto store8 = [&](int i0) {
             uint64_t kv[8], dst[8];
             bool inner[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) kv[i] = s_buf[tid + (i0 + i) * NT1];
+            for (int i = 0; i < 8; ++i) {
+                if constexpr (PERM) {
+                    // slots past the tile hold stale entries: masked into the tables
+                    const uint32_t e = s_perm[tid + (i0 + i) * NT1];
+                    kv[i] = s_slo[e & 255u] + s_shi[(e >> 8) & (KPTP - 1)];
+                } else {
+                    kv[i] = s_buf[tid + (i0 + i) * NT1];
+                }
+            }
             // a key whose 128-byte line lies inside its run [g0, g1) (all 16
             // keys of the line come from this store phase) is streamed out;
             // the run's end lines, shared with other workgroups' runs, are
@@ -319,6 +344,15 @@ __global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(2))) void k
                     if (inner[i]) __builtin_nontemporal_store(kv[i], &keys_out[dst[i]]);
                     else keys_out[dst[i]] = kv[i];
                 }
+        };
+        // the permutation tile's groups one after another (its registers stay
+        // few); the tile of keys has all groups' loads in flight at once
+        if constexpr (PERM) {
+#pragma unroll 1
+            for (int i0 = 0; i0 < KPT; i0 += 8) store8(i0);
+        } else {
+#pragma unroll
+            for (int i0 = 0; i0 < KPT; i0 += 8) store8(i0);
         }
         __syncthreads();
         for (int b = tid; b < nb; b += NT1) {
