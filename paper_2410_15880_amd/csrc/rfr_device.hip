@@ -172,7 +172,7 @@ __global__ void k_init(JobArgs Jarg, Multi M) {
 // gray(h) = h ^ (h >> 1), so going from h to h+1 flips exactly bit ctz(h+1) and
 // changes the high sum by one wavefront-uniform +-w.
 template <bool COUNT, int NBMAX, bool MULTI>
-__global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(!COUNT && NBMAX == NT1 ? 4 : 2))) void k_enum(JobArgs Jarg, Multi M) {
+__global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(!COUNT && NBMAX == NT1 ? 3 : 2))) void k_enum(JobArgs Jarg, Multi M) {
     const JobArgs *Jp;
     uint32_t wg;
     if (!pick<MULTI>(Jarg, M, COUNT ? ST_COUNT : ST_ENUM, Jp, wg)) return;
@@ -205,12 +205,14 @@ __global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(!COUNT && N
     // permutation, not as keys: a key is its lane's low sum plus its step's
     // high sum (the same for the whole workgroup), so sorted slot p holds
     // (step << 8 | lane) and the store phase rebuilds the key from two small
-    // tables.  16 KB of LDS per tile instead of 64 KB and no keys held in
-    // registers: four workgroups per CU instead of two (0.306 -> 0.281 ms per
-    // degree-100 search).  With more buckets (2^12-2^17 keys per bucket in
-    // runs of a few keys) the tile of keys was faster and is kept.
+    // tables.  Two bytes of LDS per key instead of eight and no keys held in
+    // registers, so a tile takes 64 steps (16,384 keys, runs of ~128 keys per
+    // bucket) at three workgroups per CU: 0.268 ms per degree-100 search
+    // against 0.306 with 8192-key tiles of keys at two (0.281 with 32-step
+    // permutation tiles at four).  With more buckets (2^12-2^17 keys per
+    // bucket in runs of a few keys) the tile of keys was faster and is kept.
     constexpr bool PERM = !COUNT && NBMAX == NT1;
-    constexpr int KPTP = KPT1;  // Gray steps per partition tile
+    constexpr int KPTP = 64;  // Gray steps per permutation tile (16,384 keys: runs of ~128 keys per bucket)
     __shared__ uint64_t s_buf[COUNT || PERM ? 1 : T1];
     __shared__ uint16_t s_perm[PERM ? NT1 * KPTP : 1];
     __shared__ uint64_t s_slo[PERM ? NT1 : 1];
@@ -248,8 +250,8 @@ __global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(!COUNT && N
     // buckets, where its LDS counters are contended, 8.1 against 5.1 ms at
     // n = 65); the partition pass keeps KPT1-step tiles, whose longer runs per
     // bucket store faster than more waves would gain.
-    constexpr int KPT = COUNT && NBMAX == NT1 ? 16 : KPT1;
-    static_assert(COUNT || KPT == KPTP, "the partition pass's tables hold one tile");
+    constexpr int KPT = COUNT && NBMAX == NT1 ? 16 : (PERM ? KPTP : KPT1);
+    static_assert(!PERM || KPT == KPTP, "the permutation tables hold one tile");
     constexpr int LOGK = __builtin_ctz(KPT);
     static_assert((1 << LOGK) == KPT && (KPT1 * TILES1) % KPT == 0, "tiles of a power-of-two number of Gray steps");
     const int mh = H.m - H.L;
@@ -260,7 +262,7 @@ __global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(!COUNT && N
     for (uint64_t h = h0; h < h1; h += KPT) {
         const int ns = (int)min((uint64_t)KPT, h1 - h);
         // each key's level-1 digit is counted (and, in the partition pass,
-        // ranked within its digit: d << 13 | rank, a tile holding at most 2^13
+        // ranked within its digit: d << 14 | rank, a tile holding at most 2^14
         // keys and 2^12 digits) as the Gray walk produces it
         uint32_t pk[COUNT ? 1 : KPT];
         uint64_t key_s[COUNT || PERM ? 1 : KPT];  // the keys, for a tile of keys
@@ -271,7 +273,7 @@ __global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(!COUNT && N
             if (act && k < ns) {
                 const uint32_t d = dig(key, sh1, m1);
                 if constexpr (COUNT) atomicAdd(&s_cnt[d], 1u);
-                else pk[k] = (d << 13) | atomicAdd(&s_cnt[d], 1u);
+                else pk[k] = (d << 14) | atomicAdd(&s_cnt[d], 1u);
             }
             if (PERM && tid == 0 && k < ns) s_shi[k] = shi;  // the same for every lane
             const uint64_t t = h + k + 1;
@@ -298,7 +300,7 @@ __global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(!COUNT && N
 #pragma unroll
         for (int k = 0; k < KPT; ++k)
             if (act && k < ns) {
-                const uint32_t slot = s_off[pk[k] >> 13] + (pk[k] & 8191u);
+                const uint32_t slot = s_off[pk[k] >> 14] + (pk[k] & 16383u);
                 if constexpr (PERM) s_perm[slot] = (uint16_t)((k << 8) | tid);
                 else s_buf[slot] = key_s[k];
             }
