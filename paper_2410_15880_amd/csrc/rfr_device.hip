@@ -12,7 +12,8 @@
 //   S1 k_scan_cols    per-bucket exclusive prefix over WGs
 //   S2 k_scan_buckets bucket starts and level-2 tile table
 //   K1 k_enum<false>  Gray-code enumeration, LDS counting sort of each tile by
-//                     the level-1 digit, run-coalesced stores into buckets
+//                     the level-1 digit (the tile held as a (step, lane)
+//                     permutation), run-coalesced stores into buckets
 //   K2 k_tile2        LDS counting sort of each bucket tile by the level-2
 //                     digit, written back in place + per-digit tile offsets
 //   K3 k_join         per sub-bucket (level-1 + level-2 prefix): gather both
@@ -172,7 +173,7 @@ __global__ void k_init(JobArgs Jarg, Multi M) {
 // gray(h) = h ^ (h >> 1), so going from h to h+1 flips exactly bit ctz(h+1) and
 // changes the high sum by one wavefront-uniform +-w.
 template <bool COUNT, int NBMAX, bool MULTI>
-__global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(!COUNT && NBMAX == NT1 ? 3 : 2))) void k_enum(JobArgs Jarg, Multi M) {
+__global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(!COUNT ? 3 : 2))) void k_enum(JobArgs Jarg, Multi M) {
     const JobArgs *Jp;
     uint32_t wg;
     if (!pick<MULTI>(Jarg, M, COUNT ? ST_COUNT : ST_ENUM, Jp, wg)) return;
@@ -201,22 +202,19 @@ __global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(!COUNT && N
     __shared__ uint32_t s_off[NBMAX];
     __shared__ uint64_t s_cur[COUNT ? 1 : NBMAX];
     __shared__ uint64_t s_tmp[NT1 / 64 + 1];
-    // With 2^8 buckets the partition pass keeps the tile in LDS as a
-    // permutation, not as keys: a key is its lane's low sum plus its step's
-    // high sum (the same for the whole workgroup), so sorted slot p holds
-    // (step << 8 | lane) and the store phase rebuilds the key from two small
-    // tables.  Two bytes of LDS per key instead of eight and no keys held in
-    // registers, so a tile takes 64 steps (16,384 keys, runs of ~128 keys per
-    // bucket) at three workgroups per CU: 0.268 ms per degree-100 search
-    // against 0.306 with 8192-key tiles of keys at two (0.281 with 32-step
-    // permutation tiles at four).  With more buckets (2^12-2^17 keys per
-    // bucket in runs of a few keys) the tile of keys was faster and is kept.
-    constexpr bool PERM = !COUNT && NBMAX == NT1;
-    constexpr int KPTP = 64;  // Gray steps per permutation tile (16,384 keys: runs of ~128 keys per bucket)
-    __shared__ uint64_t s_buf[COUNT || PERM ? 1 : T1];
-    __shared__ uint16_t s_perm[PERM ? NT1 * KPTP : 1];
-    __shared__ uint64_t s_slo[PERM ? NT1 : 1];
-    __shared__ uint64_t s_shi[PERM ? KPTP : 1];
+    // The partition pass keeps the tile in LDS as a permutation, not as
+    // keys: a key is its lane's low sum plus its step's high sum (the same
+    // for the whole workgroup), so sorted slot p holds (step << 8 | lane) and
+    // the store phase rebuilds the key from two small tables.  Two bytes of
+    // LDS per key instead of eight and no keys held in registers, so a tile
+    // takes 64 steps (16,384 keys: runs per bucket twice as long) at more
+    // workgroups per CU.  Per degree-100 search 0.268 ms against 0.306 with
+    // 8192-key tiles of keys; with 2^10 and 2^11 buckets (halves of 2^30 to
+    // 2^33 keys) 9.4 and 44 ms against 12.4 and 54.
+    constexpr int KPTP = 64;  // Gray steps per partition tile
+    __shared__ uint16_t s_perm[COUNT ? 1 : NT1 * KPTP];
+    __shared__ uint64_t s_slo[COUNT ? 1 : NT1];
+    __shared__ uint64_t s_shi[COUNT ? 1 : KPTP];
 
     if (tid < H.m) s_w[tid] = J.wts[blockIdx.y][tid];
     for (int b = tid; b < nb; b += NT1) {
@@ -234,7 +232,7 @@ __global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(!COUNT && N
     uint64_t slo = J.kbase[blockIdx.y];
     for (int i = 0; i < H.L; ++i)
         if ((tid >> i) & 1) slo += s_w[i];
-    if (PERM && act) s_slo[tid] = slo;
+    if (!COUNT && act) s_slo[tid] = slo;
     const uint64_t h0 = (uint64_t)wg * H.spw;
     const uint64_t h1 = min(h0 + (uint64_t)H.spw, H.steps);
     uint64_t g = h0 ^ (h0 >> 1);
@@ -250,8 +248,8 @@ __global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(!COUNT && N
     // buckets, where its LDS counters are contended, 8.1 against 5.1 ms at
     // n = 65); the partition pass keeps KPT1-step tiles, whose longer runs per
     // bucket store faster than more waves would gain.
-    constexpr int KPT = COUNT && NBMAX == NT1 ? 16 : (PERM ? KPTP : KPT1);
-    static_assert(!PERM || KPT == KPTP, "the permutation tables hold one tile");
+    constexpr int KPT = COUNT ? (NBMAX == NT1 ? 16 : KPT1) : KPTP;
+    static_assert((KPT1 * TILES1) % KPTP == 0, "ranges of whole partition tiles");
     constexpr int LOGK = __builtin_ctz(KPT);
     static_assert((1 << LOGK) == KPT && (KPT1 * TILES1) % KPT == 0, "tiles of a power-of-two number of Gray steps");
     const int mh = H.m - H.L;
@@ -265,17 +263,15 @@ __global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(!COUNT && N
         // ranked within its digit: d << 14 | rank, a tile holding at most 2^14
         // keys and 2^12 digits) as the Gray walk produces it
         uint32_t pk[COUNT ? 1 : KPT];
-        uint64_t key_s[COUNT || PERM ? 1 : KPT];  // the keys, for a tile of keys
 #pragma unroll
         for (int k = 0; k < KPT; ++k) {
             const uint64_t key = slo + shi;
-            if constexpr (!COUNT && !PERM) key_s[k] = key;
             if (act && k < ns) {
                 const uint32_t d = dig(key, sh1, m1);
                 if constexpr (COUNT) atomicAdd(&s_cnt[d], 1u);
                 else pk[k] = (d << 14) | atomicAdd(&s_cnt[d], 1u);
             }
-            if (PERM && tid == 0 && k < ns) s_shi[k] = shi;  // the same for every lane
+            if (!COUNT && tid == 0 && k < ns) s_shi[k] = shi;  // the same for every lane
             const uint64_t t = h + k + 1;
             if (k < ns && t < h1) {
                 const int b = k < KPT - 1 ? __builtin_ctz(k + 1) : __builtin_ctzll(t);
@@ -301,8 +297,7 @@ __global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(!COUNT && N
         for (int k = 0; k < KPT; ++k)
             if (act && k < ns) {
                 const uint32_t slot = s_off[pk[k] >> 14] + (pk[k] & 16383u);
-                if constexpr (PERM) s_perm[slot] = (uint16_t)((k << 8) | tid);
-                else s_buf[slot] = key_s[k];
+                s_perm[slot] = (uint16_t)((k << 8) | tid);
             }
         // destination of tile slot p of bucket d: s_cur[d] - s_off[d] + p, the
         // cursor first stepping down by the run length when filling downwards
@@ -318,13 +313,9 @@ __global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(!COUNT && N
             bool inner[8];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                if constexpr (PERM) {
-                    // slots past the tile hold stale entries: masked into the tables
-                    const uint32_t e = s_perm[tid + (i0 + i) * NT1];
-                    kv[i] = s_slo[e & 255u] + s_shi[(e >> 8) & (KPTP - 1)];
-                } else {
-                    kv[i] = s_buf[tid + (i0 + i) * NT1];
-                }
+                // slots past the tile hold stale entries: masked into the tables
+                const uint32_t e = s_perm[tid + (i0 + i) * NT1];
+                kv[i] = s_slo[e & 255u] + s_shi[(e >> 8) & (KPTP - 1)];
             }
             // a key whose 128-byte line lies inside its run [g0, g1) (all 16
             // keys of the line come from this store phase) is streamed out;
@@ -347,15 +338,9 @@ __global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(!COUNT && N
                     else keys_out[dst[i]] = kv[i];
                 }
         };
-        // the permutation tile's groups one after another (its registers stay
-        // few); the tile of keys has all groups' loads in flight at once
-        if constexpr (PERM) {
+        // the groups one after another: few registers, more workgroups
 #pragma unroll 1
-            for (int i0 = 0; i0 < KPT; i0 += 8) store8(i0);
-        } else {
-#pragma unroll
-            for (int i0 = 0; i0 < KPT; i0 += 8) store8(i0);
-        }
+        for (int i0 = 0; i0 < KPT; i0 += 8) store8(i0);
         __syncthreads();
         for (int b = tid; b < nb; b += NT1) {
             s_cur[b] += s_off[b] + (back ? 0u : s_cnt[b]);
