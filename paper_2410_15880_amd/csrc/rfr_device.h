@@ -16,7 +16,7 @@ namespace dev {
 // ---- K0/K1/K4: Gray-code enumeration (256 lanes own the low 8 pattern bits)
 constexpr int NT1 = 256;          // threads per workgroup
 constexpr int KPT1 = 32;          // Gray steps per thread per tile of the count pass (with over 2^8 buckets)
-constexpr int TILES1 = 8;         // KPT1-step tiles per K0/K1 workgroup: KPT1 * TILES1 Gray steps each
+constexpr int TILES1 = 8;         // KPT1-step tiles per K0/K1 workgroup of a half above 2^28 keys
 constexpr int MAXB1_LOG = 12;     // level-1 digit bits (buckets) at most (12 only for halves of 2^34 keys)
 constexpr int MAXB1 = 1 << MAXB1_LOG;
 // ---- K2: per-bucket tile sort by the level-2 digit

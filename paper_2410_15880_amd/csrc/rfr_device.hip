@@ -1414,7 +1414,12 @@ static void plan_half(int m, HalfPlan &h) {
     h.L = m < 8 ? m : 8;
     h.N = 1ull << m;
     h.steps = 1ull << (m - h.L);
-    h.spw = (uint32_t)(KPT1 * TILES1);
+    // Gray steps per K0/K1/K4 workgroup: one 64-step K1 tile for halves of at
+    // most 2^28 keys (finer work units leave a smaller tail on the last round
+    // of workgroups: K1 0.272 -> 0.241 ms per degree-100 search, the column
+    // scan over the per-workgroup histograms 6 -> 14 us); four tiles above,
+    // where the histograms (2^B1 buckets x workgroups) would grow to GBs.
+    h.spw = (uint32_t)(m <= 28 ? 64 : KPT1 * TILES1);
     h.nwg1 = (uint32_t)((h.steps + h.spw - 1) / h.spw);
 }
 
