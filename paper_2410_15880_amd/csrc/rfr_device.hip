@@ -368,6 +368,32 @@ __global__ __launch_bounds__(NT1) void k_scan_cols(JobArgs Jarg, Multi M) {
     if (b >= (1 << J.B1)) return;
     __shared__ uint64_t s_tmp[NT1 / 64 + 1];
     uint64_t *col = H.hist1 + (size_t)b * H.nwg1;
+    constexpr uint32_t SCAN_LDS = 4096;
+    if (H.nwg1 <= SCAN_LDS) {
+        // the column staged in LDS by coalesced loads; each thread scans a
+        // contiguous chunk, one block scan joins the chunks (one block scan
+        // instead of one per 256 entries).  One pad entry per 32 keeps the
+        // threads' chunk strides off a single bank.
+        __shared__ uint64_t s_col[SCAN_LDS + SCAN_LDS / 32];
+        auto at = [](uint32_t i) { return i + (i >> 5); };
+        const uint32_t n = H.nwg1, per = (n + NT1 - 1) / NT1;
+        for (uint32_t i = threadIdx.x; i < n; i += NT1) s_col[at(i)] = col[i];
+        __syncthreads();
+        const uint32_t c0 = min(threadIdx.x * per, n), c1 = min(c0 + per, n);
+        uint64_t sum = 0;
+        for (uint32_t i = c0; i < c1; ++i) sum += s_col[at(i)];
+        uint64_t tot;
+        uint64_t run = block_excl_scan<NT1>(sum, s_tmp, &tot);
+        for (uint32_t i = c0; i < c1; ++i) {
+            const uint64_t v = s_col[at(i)];
+            s_col[at(i)] = run;
+            run += v;
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < n; i += NT1) col[i] = s_col[at(i)];
+        if (threadIdx.x == 0) H.bstart[b] = tot;
+        return;
+    }
     uint64_t carry = 0;
     for (uint32_t base = 0; base < H.nwg1; base += NT1) {
         const uint32_t i = base + threadIdx.x;
