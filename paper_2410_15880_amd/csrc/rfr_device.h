@@ -49,7 +49,7 @@ constexpr int MAX_SEARCH_N = 2 * MAX_HALF + 2;  // elements of a search (n - 1 =
 constexpr int MAX_CHUNK_BITS = 8; // half A streamed in at most 2^8 chunks
 constexpr int RECOVER_FEW = 128;  // candidate key pairs handled by the meet-in-the-middle recovery
 constexpr int RECOVER_WGS = 512;  // workgroups per half of a single search's many-candidate recovery
-constexpr int SPT4 = 16;          // Gray steps per thread in that recovery
+constexpr int SPT4 = 2;           // Gray steps per thread in that recovery (enough workgroups to fill the chip)
 
 struct HalfArgs {
     uint64_t *keys;      // [N] partitioned keys

@@ -1204,22 +1204,46 @@ __global__ __launch_bounds__(NT1) void k_recover_few(JobArgs Jarg, Multi M) {
     for (int i = 0; i < H.m - H.L; ++i)
         if ((g >> i) & 1) shi += s_w[H.L + i];
     for (uint64_t h = h0; h < h1; ++h) {
-        for (uint32_t c = 0; c < cnt; ++c) {
-            if (s_dup[c]) continue;
-            const uint64_t key = s_list[c];
-            const uint64_t x = key - shi;
-            int lo = 0, hi = nl;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (s_sorted[mid] < x) lo = mid + 1;
-                else hi = mid;
+        // the lower bounds of four candidates at a time, interleaved: four
+        // independent chains of LDS reads in flight instead of one
+        for (uint32_t c0 = 0; c0 < cnt; c0 += 4) {
+            uint64_t x[4];
+            int lo[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                x[j] = s_list[min(c0 + j, (uint32_t)cnt - 1)] - shi;  // past the list: a repeat, ignored
+                lo[j] = 0;
             }
-            for (int q = lo; q < nl && s_sorted[q] == x; ++q) {
-                const uint64_t pat = ((uint64_t)s_lane[q] | (g << H.L)) | J.pbase[half];
-                const uint64_t r = atomicAdd((unsigned long long *)&J.rec_count[half], 1ull);
-                if (r < J.kcap) {
-                    J.rec[((size_t)half * J.kcap + r) * 2] = key;
-                    J.rec[((size_t)half * J.kcap + r) * 2 + 1] = pat;
+            if (nl == 256) {
+#pragma unroll
+                for (int step = 128; step > 0; step >>= 1)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (s_sorted[lo[j] + step - 1] < x[j]) lo[j] += step;
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    int l = 0, r = nl;
+                    while (l < r) {
+                        const int mid = (l + r) >> 1;
+                        if (s_sorted[mid] < x[j]) l = mid + 1;
+                        else r = mid;
+                    }
+                    lo[j] = l;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t c = c0 + j;
+                if (c >= cnt || s_dup[c]) continue;
+                const uint64_t key = s_list[c];
+                for (int q = lo[j]; q < nl && s_sorted[q] == x[j]; ++q) {
+                    const uint64_t pat = ((uint64_t)s_lane[q] | (g << H.L)) | J.pbase[half];
+                    const uint64_t r = atomicAdd((unsigned long long *)&J.rec_count[half], 1ull);
+                    if (r < J.kcap) {
+                        J.rec[((size_t)half * J.kcap + r) * 2] = key;
+                        J.rec[((size_t)half * J.kcap + r) * 2 + 1] = pat;
+                    }
                 }
             }
         }
