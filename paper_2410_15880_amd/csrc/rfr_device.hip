@@ -259,18 +259,13 @@ __global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(!COUNT ? 3 
 
     for (uint64_t h = h0; h < h1; h += KPT) {
         const int ns = (int)min((uint64_t)KPT, h1 - h);
-        // each key's level-1 digit is counted (and, in the partition pass,
-        // ranked within its digit: d << 14 | rank, a tile holding at most 2^14
-        // keys and 2^12 digits) as the Gray walk produces it
-        uint32_t pk[COUNT ? 1 : KPT];
+        // each key's level-1 digit is counted as the Gray walk produces it;
+        // the partition pass ranks the keys in a second pass below, so no
+        // rank is held in registers across the tile
 #pragma unroll
         for (int k = 0; k < KPT; ++k) {
             const uint64_t key = slo + shi;
-            if (act && k < ns) {
-                const uint32_t d = dig(key, sh1, m1);
-                if constexpr (COUNT) atomicAdd(&s_cnt[d], 1u);
-                else pk[k] = (d << 14) | atomicAdd(&s_cnt[d], 1u);
-            }
+            if (act && k < ns) atomicAdd(&s_cnt[dig(key, sh1, m1)], 1u);
             if (!COUNT && tid == 0 && k < ns) s_shi[k] = shi;  // the same for every lane
             const uint64_t t = h + k + 1;
             if (k < ns && t < h1) {
@@ -293,15 +288,29 @@ __global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(!COUNT ? 3 
             __syncthreads();
             lds_excl_scan<NT1, NBMAX / NT1>(s_off, nb, s_tmp);
         }
-#pragma unroll
-        for (int k = 0; k < KPT; ++k)
-            if (act && k < ns) {
-                const uint32_t slot = s_off[pk[k] >> 14] + (pk[k] & 16383u);
+        // second pass over the tile: each key, rebuilt from its lane's and
+        // step's sums, takes the next slot of its bucket (s_off as cursor).
+        // Holding the 64 ranks of the first pass in registers instead took
+        // 168 VGPRs (three workgroups per CU); with this pass K1 holds 84 and
+        // LDS allows four: 0.243 -> 0.198 ms per degree-100 search.  The order
+        // of keys inside a bucket is free: K2 sorts them and every later
+        // result is a set.
+        if (act) {
+#pragma unroll 8
+            for (int k = 0; k < ns; ++k) {
+                const uint32_t slot = atomicAdd(&s_off[dig(slo + s_shi[k], sh1, m1)], 1u);
                 s_perm[slot] = (uint16_t)((k << 8) | tid);
             }
-        // destination of tile slot p of bucket d: s_cur[d] - s_off[d] + p, the
-        // cursor first stepping down by the run length when filling downwards
-        for (int b = tid; b < nb; b += NT1) s_cur[b] -= s_off[b] + (back ? s_cnt[b] : 0u);
+        }
+        __syncthreads();
+        // s_off back to the bucket starts; destination of tile slot p of
+        // bucket d: s_cur[d] - s_off[d] + p, the cursor first stepping down by
+        // the run length when filling downwards
+        for (int b = tid; b < nb; b += NT1) {
+            const uint32_t st = s_off[b] - s_cnt[b];
+            s_off[b] = st;
+            s_cur[b] -= st + (back ? s_cnt[b] : 0u);
+        }
         __syncthreads();
         const int tile = ns * nl;
         // in groups of 8 slots: LDS reads first (slots past the tile read stale
