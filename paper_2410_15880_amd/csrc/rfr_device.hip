@@ -210,8 +210,12 @@ __global__ __launch_bounds__(NT1) __attribute__((amdgpu_waves_per_eu(!COUNT ? 3 
     // takes 64 steps (16,384 keys: runs per bucket twice as long) at more
     // workgroups per CU.  Per degree-100 search 0.268 ms against 0.306 with
     // 8192-key tiles of keys; with 2^10 and 2^11 buckets (halves of 2^30 to
-    // 2^33 keys) 9.4 and 44 ms against 12.4 and 54.
-    constexpr int KPTP = 64;  // Gray steps per partition tile
+    // 2^33 keys) 9.4 and 44 ms against 12.4 and 54.  With 2^11 buckets and
+    // more a tile takes 128 steps (one workgroup per CU, runs of ~8 keys per
+    // bucket instead of ~4): K1 at n = 65 52.2-53.6 -> 48.5-49 ms; with 2^10
+    // buckets the 64-step tiles' two workgroups per CU are faster (halves of
+    // 2^29 keys 11.3 against 13.0 ms per search).
+    constexpr int KPTP = NBMAX >= 2048 ? 128 : 64;  // Gray steps per partition tile
     __shared__ uint16_t s_perm[COUNT ? 1 : NT1 * KPTP];
     __shared__ uint64_t s_slo[COUNT ? 1 : NT1];
     __shared__ uint64_t s_shi[COUNT ? 1 : KPTP];
