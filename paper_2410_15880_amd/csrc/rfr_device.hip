@@ -480,8 +480,7 @@ __global__ __launch_bounds__(NT) void k_tile2(JobArgs Jarg, Multi M) {
     const int tid = threadIdx.x;
 
     __shared__ uint64_t s_buf[TT];
-    __shared__ uint32_t s_cnt[NBMAX];
-    __shared__ uint32_t s_off[NBMAX];
+    __shared__ uint32_t s_cnt[NBMAX];  // digit counts, then (scanned in place) digit offsets
     __shared__ uint64_t s_tmp[NT / 64 + 1];
     __shared__ int s_b;
 
@@ -515,13 +514,11 @@ __global__ __launch_bounds__(NT) void k_tile2(JobArgs Jarg, Multi M) {
         if (p < len) rank[k] = atomicAdd(&s_cnt[dig(key[k], sh2, m2)], 1u);
     }
     __syncthreads();
-    for (int d = tid; d < nd; d += NT) s_off[d] = s_cnt[d];
-    __syncthreads();
-    lds_excl_scan<NT, (NBMAX + NT - 1) / NT>(s_off, nd, s_tmp);
+    lds_excl_scan<NT, (NBMAX + NT - 1) / NT>(s_cnt, nd, s_tmp);
 #pragma unroll
     for (int k = 0; k < KPT2; ++k) {
         const int p = tid + k * NT;
-        if (p < len) s_buf[s_off[dig(key[k], sh2, m2)] + rank[k]] = key[k];
+        if (p < len) s_buf[s_cnt[dig(key[k], sh2, m2)] + rank[k]] = key[k];
     }
     __syncthreads();
     uint64_t kv[KPT2];
@@ -533,7 +530,7 @@ __global__ __launch_bounds__(NT) void k_tile2(JobArgs Jarg, Multi M) {
 #pragma unroll
     for (int k = 0; k < KPT2; ++k)
         if (tid + k * NT < len) __builtin_nontemporal_store(kv[k], &keys[tid + k * NT]);
-    for (int d = tid; d < nd; d += NT) H.digstart[(size_t)d * H.ntile2_max + tile] = (uint16_t)s_off[d];
+    for (int d = tid; d < nd; d += NT) H.digstart[(size_t)d * H.ntile2_max + tile] = (uint16_t)s_cnt[d];
     if (tid == 0) H.digstart[(size_t)nd * H.ntile2_max + tile] = (uint16_t)len;
 }
 
@@ -1665,16 +1662,20 @@ static hipError_t launch_all(const JobArgs &J, const Multi &M, const uint32_t *g
     else if (maxB1 <= 11) hipLaunchKernelGGL((k_enum<false, 2048, MULTI>), dim3(grids[ST_ENUM], nh), dim3(NT1), 0, st, J, M);
     else hipLaunchKernelGGL((k_enum<false, MAXB1, MULTI>), dim3(grids[ST_ENUM], nh), dim3(NT1), 0, st, J, M);
     rec(3);
-    // the workgroup holds the launch's largest tile (a job's tiles may be smaller)
+    // the workgroup holds the launch's largest tile (a job's tiles may be
+    // smaller); 2^11 digits get their own instantiation, whose LDS (81 KB with
+    // 8192-key tiles) lets two workgroups share a CU where 4096 digits allow one
     if (maxT2 > T2_LOG) {
         constexpr int NT = (1 << T2_BIG_LOG) / KPT2;
         if (maxB2 <= 8) hipLaunchKernelGGL((k_tile2<256, NT, MULTI>), dim3(grids[ST_TILE2], nh), dim3(NT), 0, st, J, M);
         else if (maxB2 <= 10) hipLaunchKernelGGL((k_tile2<1024, NT, MULTI>), dim3(grids[ST_TILE2], nh), dim3(NT), 0, st, J, M);
+        else if (maxB2 <= 11) hipLaunchKernelGGL((k_tile2<2048, NT, MULTI>), dim3(grids[ST_TILE2], nh), dim3(NT), 0, st, J, M);
         else hipLaunchKernelGGL((k_tile2<MAXB2, NT, MULTI>), dim3(grids[ST_TILE2], nh), dim3(NT), 0, st, J, M);
     } else {
         constexpr int NT = (1 << T2_LOG) / KPT2;
         if (maxB2 <= 8) hipLaunchKernelGGL((k_tile2<256, NT, MULTI>), dim3(grids[ST_TILE2], nh), dim3(NT), 0, st, J, M);
         else if (maxB2 <= 10) hipLaunchKernelGGL((k_tile2<1024, NT, MULTI>), dim3(grids[ST_TILE2], nh), dim3(NT), 0, st, J, M);
+        else if (maxB2 <= 11) hipLaunchKernelGGL((k_tile2<2048, NT, MULTI>), dim3(grids[ST_TILE2], nh), dim3(NT), 0, st, J, M);
         else hipLaunchKernelGGL((k_tile2<MAXB2, NT, MULTI>), dim3(grids[ST_TILE2], nh), dim3(NT), 0, st, J, M);
     }
     rec(4);
