@@ -454,7 +454,7 @@ __global__ __launch_bounds__(NT1) void k_scan_buckets(JobArgs Jarg, Multi M) {
 // the level-2 digit in LDS, written back in place; digstart[d][tile] = offset
 // of digit d inside the tile, digstart[nd][tile] = tile length.
 template <int NBMAX, int NT, bool MULTI>
-__global__ __launch_bounds__(NT) void k_tile2(JobArgs Jarg, Multi M) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ? 8 : 1))) void k_tile2(JobArgs Jarg, Multi M) {
     constexpr int TT = NT * KPT2;
     const JobArgs *Jp;
     uint32_t tile;
@@ -502,11 +502,24 @@ __global__ __launch_bounds__(NT) void k_tile2(JobArgs Jarg, Multi M) {
 
     uint64_t key[KPT2];
     uint32_t rank[KPT2];
-    // all loads first (independent, in flight together), then the ranks
+    // all loads first (independent, in flight together), then the ranks.  In
+    // 1024-thread workgroups no branch: a slot past the tile's end re-reads
+    // its last key (a tile holds at least one) and is not ranked.  Behind a
+    // branch per slot the compiler moved the first slot's key between
+    // registers before issuing the other loads, waiting for it: one more
+    // memory round trip per workgroup.  (The 512-thread instantiations keep
+    // the branches: without them their registers outgrow four workgroups per
+    // CU.)
+    if constexpr (NT >= 1024) {
 #pragma unroll
-    for (int k = 0; k < KPT2; ++k) {
-        const int p = tid + k * NT;
-        if (p < len) key[k] = __builtin_nontemporal_load(&keys[p]);
+        for (int k = 0; k < KPT2; ++k)
+            key[k] = __builtin_nontemporal_load(&keys[min((uint32_t)(tid + k * NT), (uint32_t)len - 1u)]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < KPT2; ++k) {
+            const int p = tid + k * NT;
+            if (p < len) key[k] = __builtin_nontemporal_load(&keys[p]);
+        }
     }
 #pragma unroll
     for (int k = 0; k < KPT2; ++k) {
