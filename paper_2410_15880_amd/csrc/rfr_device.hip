@@ -669,7 +669,8 @@ __device__ __forceinline__ void gather_regs(const JobArgs &J, int d, const SubRe
                 }
             }
         }
-        for (int i = tid; i < NH * MW; i += NT3) s_mapw[i] = 0;
+        // cleared 16 bytes at a time (the map is 16-byte aligned in LDS)
+        for (int i = tid; i < NH * MW / 4; i += NT3) reinterpret_cast<uint4 *>(s_mapw)[i] = make_uint4(0, 0, 0, 0);
         uint64_t tot;
         const uint64_t pre_off = block_excl_scan<NT3>((uint64_t)len[0] | ((uint64_t)len[1] << 32), s_tmp, &tot);
         const uint32_t cl[2] = {(uint32_t)tot, (uint32_t)(tot >> 32)};
@@ -854,11 +855,11 @@ __device__ __forceinline__ void mark_window(uint32_t *bm, uint32_t c, bool lo, b
 }
 
 // LDS of a sorting (expansion) K3 workgroup: the sub-bucket's keys and bins.
-struct SortLds {
+struct alignas(16) SortLds {
     uint64_t b[CAP3];
     uint32_t bin[NB3 + 1];
     uint32_t src[2][MAXT];
-    uint32_t mapw[2 * CAP3 / 4];
+    alignas(16) uint32_t mapw[2 * CAP3 / 4];
     uint64_t tmp[NT3 / 64 + 2];
     uint32_t nl[2];
 };
@@ -866,7 +867,7 @@ struct SortLds {
 // LDS of one joining K3 workgroup, sized so that six workgroups fit a CU.
 // `u` holds either the semi-join's bitmap and two lists or, on the exact
 // fallback, a chunk of B' keys.
-struct JoinLds {
+struct alignas(16) JoinLds {
     static constexpr uint32_t NWD = (1u << CB3) / 32;  // bitmap words
     union {
         struct {
@@ -877,7 +878,7 @@ struct JoinLds {
         uint64_t keys[FB3];
     } u;
     uint32_t src[2][MAXT];
-    uint32_t mapw[2 * CAP3 / 4];
+    alignas(16) uint32_t mapw[2 * CAP3 / 4];
     uint64_t tmp[NT3 / 64 + 2];
     uint32_t nl[2];
 };
@@ -1069,7 +1070,8 @@ __device__ __forceinline__ void join_sub(const JobArgs &J, uint32_t s, int b, in
     if constexpr (SORT_OUT) {
         for (int i = tid; i < NB3; i += NT3) L.bin[i] = 0;
     } else {
-        for (uint32_t i = tid; i < 2 * JoinLds::NWD; i += NT3) L.u.sj.bm[i] = 0;
+        for (uint32_t i = tid; i < 2 * JoinLds::NWD / 4; i += NT3)
+            reinterpret_cast<uint4 *>(L.u.sj.bm)[i] = make_uint4(0, 0, 0, 0);
         if (tid < 2) L.nl[tid] = 0;
     }
     uint32_t n[2];
